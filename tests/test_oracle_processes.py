@@ -1,0 +1,291 @@
+"""Pins of the oracle's |M|^2 (CPU only).
+
+e+e- -> mu+mu- (s-channel photon + Z) and g g -> t t~ against per-event closed
+forms and total cross sections; g g -> t t~ + 1..3 gluons against gauge
+invariance, Lorentz invariance, Bose symmetry, the brute-force colour sum,
+the diagram and colour-flow counts and the published colour matrices.
+"""
+import math
+import os
+from itertools import permutations
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+MT = 173.0
+SEED = 230318244
+
+
+def mdot(a, b):
+    return a[..., 0] * b[..., 0] - a[..., 1] * b[..., 1] - a[..., 2] * b[..., 2] - a[..., 3] * b[..., 3]
+
+
+def masses_for(pdg):
+    return [MT if abs(x) == 6 else 0.0 for x in pdg[2:]]
+
+
+@pytest.fixture(scope="module")
+def procs(oracle_mod):
+    return {name: oracle_mod.Process(pdg) for name, pdg in oracle_mod.PROCESSES.items()}
+
+
+def two_body(n, sqrt_s, m, seed=1):
+    """Exactly on-shell 2 -> 2 kinematics from random angles: RAMBO's conformal
+    boost can leave momenta off shell by ~1e-12 relative for nearly collinear
+    pairs, which is too coarse for a 1e-13 closed-form pin."""
+    rng = np.random.default_rng(seed)
+    cost = rng.uniform(-1, 1, n)
+    phi = rng.uniform(0, 2 * np.pi, n)
+    e = sqrt_s / 2
+    pa = math.sqrt(e * e - m * m)
+    sint = np.sqrt(1 - cost ** 2)
+    mom = np.zeros((n, 4, 4))
+    mom[:, 0] = [e, 0, 0, e]
+    mom[:, 1] = [e, 0, 0, -e]
+    k = np.stack([np.full(n, e), pa * sint * np.cos(phi), pa * sint * np.sin(phi), pa * cost], axis=1)
+    mom[:, 2] = k
+    mom[:, 3] = k * np.array([1, -1, -1, -1])
+    return mom
+
+
+def events(oracle_mod, name, n, first=0, sqrt_s=None):
+    pdg = oracle_mod.PROCESSES[name]
+    if sqrt_s is None:
+        sqrt_s = 500.0 if name == "ee_mumu" else 1500.0
+    return oracle_mod.rambo(masses_for(pdg), sqrt_s, SEED, first, n)
+
+
+# ----------------------------------------------------------------- e+e- -> mu+mu-
+ALPHA = 1.0 / 132.5
+SW2 = 0.2222
+MZ, WZ = 91.188, 2.441
+
+
+def ee_amplitudes(s):
+    cw2 = 1 - SW2
+    gl, gr = -0.5 + SW2, SW2
+    a = lambda gi, gj: 1 / s + gi * gj / (SW2 * cw2 * (s - MZ ** 2 + 1j * MZ * WZ))
+    return {"LL": a(gl, gl), "RR": a(gr, gr), "LR": a(gl, gr), "RL": a(gr, gl)}
+
+
+def test_ee_closed_form_per_event(procs, oracle_mod):
+    mom = two_body(200, 500.0, 0.0)
+    me = procs["ee_mumu"].me(mom)
+    s = 500.0 ** 2
+    e4 = (4 * math.pi * ALPHA) ** 2
+    t = -2 * mdot(mom[:, 0], mom[:, 2])  # massless legs: (p1 - p3)^2 = -2 p1.p3
+    u = -2 * mdot(mom[:, 0], mom[:, 3])
+    A = ee_amplitudes(s)
+    ref = e4 * ((abs(A["LL"]) ** 2 + abs(A["RR"]) ** 2) * u ** 2 + (abs(A["LR"]) ** 2 + abs(A["RL"]) ** 2) * t ** 2)
+    np.testing.assert_allclose(me, ref, rtol=1e-13)
+
+
+def test_ee_per_helicity(procs, oracle_mod):
+    mom = two_body(5, 500.0, 0.0)
+    s = 500.0 ** 2
+    e4 = (4 * math.pi * ALPHA) ** 2
+    A = ee_amplitudes(s)
+    for p in mom:
+        hel = procs["ee_mumu"].me_hel(p)
+        t = -2 * mdot(p[0], p[2])
+        u = -2 * mdot(p[0], p[3])
+        # helicity index: bit (3 - leg) set for helicity +1; legs e+ e- mu+ mu-
+        expect = np.zeros(16)
+        expect[0b1010] = e4 * abs(A["LL"]) ** 2 * u ** 2  # e-_L, mu-_L
+        expect[0b0101] = e4 * abs(A["RR"]) ** 2 * u ** 2  # e-_R, mu-_R
+        expect[0b1001] = e4 * abs(A["LR"]) ** 2 * t ** 2  # e-_L, mu-_R
+        expect[0b0110] = e4 * abs(A["RL"]) ** 2 * t ** 2  # e-_R, mu-_L
+        np.testing.assert_allclose(hel, expect, rtol=1e-13, atol=0)
+        assert np.count_nonzero(hel) == 4  # the other twelve vanish exactly
+
+
+def test_ee_photon_only(oracle_mod):
+    P = oracle_mod.Process(oracle_mod.PROCESSES["ee_mumu"], z_enabled=0)
+    mom = two_body(400, 500.0, 0.0)
+    me = P.me(mom)
+    s = 500.0 ** 2
+    e4 = (4 * math.pi * ALPHA) ** 2
+    t = -2 * mdot(mom[:, 0], mom[:, 2])  # massless legs: (p1 - p3)^2 = -2 p1.p3
+    u = -2 * mdot(mom[:, 0], mom[:, 3])
+    np.testing.assert_allclose(me, 2 * e4 * (t ** 2 + u ** 2) / s ** 2, rtol=1e-13)
+    mom, w = events(oracle_mod, "ee_mumu", 20000)
+    me = P.me(mom)
+    # total cross section 4 pi alpha^2 / (3 s), Monte Carlo with RAMBO weights
+    f = w * me / (2 * s)
+    sigma, err = f.mean(), f.std() / math.sqrt(len(f))
+    assert abs(sigma - 4 * math.pi * ALPHA ** 2 / (3 * s)) < 4 * err
+
+
+# -------------------------------------------------------------------- g g -> t t~
+def esw(p):
+    s = mdot(p[:, 0] + p[:, 1], p[:, 0] + p[:, 1])
+    gs4 = (4 * math.pi * 0.118) ** 2
+    t1 = 2 * mdot(p[:, 0], p[:, 2]) / s
+    t2 = 2 * mdot(p[:, 1], p[:, 2]) / s
+    rho = 4 * MT * MT / s
+    return gs4 * (1 / (6 * t1 * t2) - 3 / 8) * (t1 ** 2 + t2 ** 2 + rho - rho ** 2 / (4 * t1 * t2))
+
+
+def test_ggtt_closed_form(procs, oracle_mod):
+    mom = two_body(400, 1500.0, MT)
+    np.testing.assert_allclose(procs["gg_tt"].me(mom), esw(mom), rtol=1e-13)
+
+
+def test_ggtt_total_cross_section(procs, oracle_mod):
+    # Combridge: sigma = pi as^2/(3s) [(1 + rho + rho^2/16) ln((1+b)/(1-b)) - b (7/4 + 31 rho/16)]
+    mom, w = events(oracle_mod, "gg_tt", 20000)
+    me = procs["gg_tt"].me(mom)
+    s = 1500.0 ** 2
+    rho = 4 * MT * MT / s
+    beta = math.sqrt(1 - rho)
+    sig = (math.pi * 0.118 ** 2 / (3 * s)) * ((1 + rho + rho ** 2 / 16) * math.log((1 + beta) / (1 - beta))
+                                               - beta * (7 / 4 + 31 * rho / 16))
+    f = w * me / (2 * s)
+    assert abs(f.mean() - sig) < 4 * f.std() / math.sqrt(len(f))
+
+
+# ------------------------------------------------------------------ multi-gluon
+COUNTS = {"gg_tt": (3, 2, 16), "gg_ttg": (16, 6, 32), "gg_ttgg": (123, 24, 64), "gg_ttggg": (1240, 120, 128)}
+
+
+@pytest.mark.parametrize("name", list(COUNTS))
+def test_counts(procs, name):
+    P = procs[name]
+    assert (P.n_diagrams, P.n_colour, P.n_hel) == COUNTS[name]
+
+
+def _golden_rows():
+    rows = {}
+    with open(os.path.join(HERE, "golden", "colour_matrices.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            v = [int(x) for x in line.split()]
+            rows[v[0]] = (v[1], sorted(v[2:]))
+    return rows
+
+
+@pytest.mark.parametrize("name,k", [("gg_tt", 2), ("gg_ttg", 3), ("gg_ttgg", 4), ("gg_ttggg", 5)])
+def test_colour_matrix(procs, name, k):
+    C, den, basis = procs[name].colour_matrix()
+    n = math.factorial(k)
+    assert C.shape == (n, n) and basis.shape == (n, k)
+    assert np.array_equal(C, C.T)
+    # diagonal N C_F^k
+    np.testing.assert_allclose(np.diag(C) / den, 3 * (4 / 3) ** k, rtol=1e-15)
+    np.linalg.cholesky(C.astype(float))  # positive definite
+    golden = _golden_rows()
+    if k in golden:
+        gden, grow = golden[k]
+        assert den == gden
+        for r in range(n):
+            assert sorted(C[r].tolist()) == grow
+
+
+def test_colour_matrix_recursion(procs):
+    """Orderings that share their first (or last) gluon: summing that gluon's
+    colour gives C_F times the entry of the k-1 gluon matrix."""
+    for name, sub in (("gg_ttggg", "gg_ttgg"), ("gg_ttgg", "gg_ttg")):
+        C, den, basis = procs[name].colour_matrix()
+        Cs, dens, bs = procs[sub].colour_matrix()
+        legs_sub = sorted(bs[0].tolist())
+        index = {tuple(b): i for i, b in enumerate(bs.tolist())}
+        checked = 0
+        for a in range(len(basis)):
+            for b in range(len(basis)):
+                sa, sb = list(basis[a]), list(basis[b])
+                for pos in (0, -1):
+                    if sa[pos] != sb[pos]:
+                        continue
+                    g = sa[pos]
+                    ra = [x for x in sa if x != g]
+                    rb = [x for x in sb if x != g]
+                    # relabel the remaining gluon legs onto the smaller process
+                    rest = sorted(ra)
+                    mp = dict(zip(rest, legs_sub))
+                    ia = index[tuple(mp[x] for x in ra)]
+                    ib = index[tuple(mp[x] for x in rb)]
+                    assert C[a, b] * dens * 3 == Cs[ia, ib] * den * 4
+                    checked += 1
+        assert checked > len(basis)
+
+
+@pytest.mark.parametrize("name,n", [("gg_tt", 8), ("gg_ttg", 8), ("gg_ttgg", 1)])
+def test_brute_force_colour_sum(procs, oracle_mod, name, n):
+    mom, _ = events(oracle_mod, name, n)
+    P = procs[name]
+    np.testing.assert_allclose(P.me(mom, colour_mode=1), P.me(mom), rtol=1e-12)
+
+
+GAUGE_CASES = [("gg_ttg", 3, None), ("gg_ttgg", 2, None), ("gg_ttggg", 1, [0, 6])]
+
+
+@pytest.mark.parametrize("name,n,legs", GAUGE_CASES)
+def test_gauge_invariance(procs, oracle_mod, name, n, legs):
+    mom, _ = events(oracle_mod, name, n)
+    P = procs[name]
+    gl = [i for i, x in enumerate(P.pdg) if x == 21] if legs is None else legs
+    for p in mom:
+        for leg in gl:
+            rep, ref = P.gauge(p, leg)
+            assert rep <= 1e-11 * p[leg][0] * ref
+
+
+def boost(mom, beta_vec):
+    b2 = beta_vec @ beta_vec
+    g = 1 / math.sqrt(1 - b2)
+    out = np.empty_like(mom)
+    bp = mom[..., 1:] @ beta_vec
+    out[..., 0] = g * (mom[..., 0] + bp)
+    out[..., 1:] = mom[..., 1:] + ((g - 1) * bp / b2 + g * mom[..., 0])[..., None] * beta_vec
+    return out
+
+
+@pytest.mark.parametrize("name,n", [("gg_tt", 20), ("gg_ttg", 10), ("gg_ttgg", 2), ("gg_ttggg", 1),
+                                    ("ee_mumu", 20)])
+def test_lorentz_invariance(procs, oracle_mod, name, n):
+    mom, _ = events(oracle_mod, name, n)
+    rng = np.random.default_rng(3)
+    d = rng.normal(size=3)
+    bvec = 0.9 * d / np.linalg.norm(d)
+    P = procs[name]
+    np.testing.assert_allclose(P.me(boost(mom, bvec)), P.me(mom), rtol=1e-12)
+
+
+@pytest.mark.parametrize("name,n", [("gg_tt", 10), ("gg_ttg", 10), ("gg_ttgg", 2), ("gg_ttggg", 1)])
+def test_bose_symmetry(procs, oracle_mod, name, n):
+    mom, _ = events(oracle_mod, name, n)
+    P = procs[name]
+    ref = P.me(mom)
+    swapped = mom.copy()
+    swapped[:, [0, 1]] = mom[:, [1, 0]]
+    np.testing.assert_allclose(P.me(swapped), ref, rtol=1e-12)
+    fin = list(range(4, P.n_ext))
+    if len(fin) > 1:
+        for perm in list(permutations(fin))[1:3]:
+            pm = mom.copy()
+            pm[:, fin] = mom[:, list(perm)]
+            np.testing.assert_allclose(P.me(pm), ref, rtol=1e-12)
+
+
+@pytest.mark.parametrize("name,n", [("gg_tt", 10), ("gg_ttg", 5), ("gg_ttgg", 2)])
+def test_long_double_agrees(procs, oracle_mod, name, n):
+    mom, _ = events(oracle_mod, name, n)
+    P = procs[name]
+    np.testing.assert_allclose(P.me(mom, precision=1), P.me(mom), rtol=1e-12)
+
+
+@pytest.mark.parametrize("name,power", [("gg_tt", 2), ("gg_ttg", 3), ("gg_ttgg", 4)])
+def test_coupling_power(oracle_mod, name, power):
+    mom, _ = events(oracle_mod, name, 3)
+    a = oracle_mod.Process(oracle_mod.PROCESSES[name], alpha_s=0.118).me(mom)
+    b = oracle_mod.Process(oracle_mod.PROCESSES[name], alpha_s=0.236).me(mom)
+    np.testing.assert_allclose(b / a, 2.0 ** power, rtol=1e-13)
+
+
+def test_unsupported_process(oracle_mod):
+    with pytest.raises(ValueError):
+        oracle_mod.Process([21, 21, 5, -5])
+    with pytest.raises(ValueError):
+        oracle_mod.Process([21, 21, 6, -6], wt=1.5)
