@@ -1,0 +1,132 @@
+/* mgme: tree-level squared matrix elements on MI355X (gfx950).
+ *
+ * C ABI of libmgme.so.  A process is built once from its external particles
+ * and couplings; a call then maps a device array of phase-space momenta to
+ * per-event |M|^2, summed over helicities and colours, in one lockstep
+ * data-parallel launch.  This is the batched matrix-element call that the
+ * paper substitutes for the event-by-event one (section 2: batches of events
+ * held in large arrays and handed to the matrix-element engine in one call),
+ * with the matrix element itself computed from Feynman diagrams and helicity
+ * amplitudes (section 1) and its colour algebra as in section 3.
+ *
+ * Conventions for every call:
+ *  - Every function returns an mgme_status; 0 is success.  No exception or
+ *    signal crosses the ABI.  mgme_last_error() returns a thread-local text
+ *    describing the last failure on the calling thread.
+ *  - Device pointers (d_*) are owned by the caller (for example
+ *    torch.Tensor.data_ptr() of a CUDA/HIP tensor); the library never frees
+ *    or retains them.  A process owns only its own host state.
+ *  - Kernels are enqueued asynchronously on `hip_stream` (a hipStream_t; NULL
+ *    is the default stream).  Nothing synchronises; an asynchronous device
+ *    fault is reported as MGME_EDEVICE by the next call.
+ *  - Momenta are FP64, structure-of-arrays: component mu (E, px, py, pz, in
+ *    GeV) of particle i (in the order of the pdg list, initial state first)
+ *    for event e is d_mom[(i*4 + mu)*ld + e].  ld >= nevt; a multiple of 64
+ *    keeps every load coalesced.
+ *  - nevt == 0 is a no-op returning MGME_OK; nevt < 0, ld < nevt or a NULL
+ *    required pointer returns MGME_EINVAL.
+ */
+#ifndef MGME_H
+#define MGME_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MGME_OK = 0,
+  MGME_EINVAL = -1,        /* bad argument (NULL, negative size, ld < nevt, bad parameter) */
+  MGME_EUNSUPPORTED = -2,  /* process, precision or parameter not supported */
+  MGME_ENOMEM = -3,        /* device allocation failed (process creation only) */
+  MGME_EDEVICE = -4        /* HIP runtime error, including a fault of an earlier launch */
+} mgme_status;
+
+typedef enum {
+  MGME_FP64 = 0, /* plain method: every step in double precision */
+  MGME_FP32 = 1, /* diagrams in single precision; momenta, propagator denominators,
+                    colour quadratic form and helicity sum in double */
+  MGME_MIXED = 2 /* single-precision diagrams with a 16-bit matrix-core colour sum (not yet available) */
+} mgme_precision;
+
+/* Couplings and masses.  alpha_s is fixed (no running).  The top width wt
+ * must be 0 (propagators of internal top quarks carry no width).  z_enabled
+ * = 0 removes Z exchange from e+e- -> mu+mu-. */
+typedef struct {
+  double alpha_s, alpha_em, sin2w, mz, wz, mt, wt;
+  int z_enabled;
+} mgme_params;
+
+typedef struct {
+  int n_ext;              /* external particles */
+  int n_diagrams;         /* tree-level Feynman diagrams */
+  int n_amp_terms;        /* diagrams with each four-gluon colour structure counted once */
+  int n_colour;           /* colour flows (trace basis) */
+  int n_hel;              /* helicity configurations, 2^n_ext */
+  int n_good_hel;         /* helicities with a non-zero contribution (see mgme_process_create) */
+  int n_currents;         /* off-shell currents evaluated per helicity */
+  int n_amp_vertices;     /* amplitude vertices evaluated per helicity */
+  double norm_factor;     /* 1 / (initial spin-colour average * final identical-particle factor) */
+  double flops_per_hel;   /* floating-point operations per event and good helicity (static tally) */
+  double flops_per_event; /* helicity-independent operations per event */
+} mgme_info;
+
+typedef struct mgme_process mgme_process;
+
+/* Builds a process from its particle list in the order initial state first
+ * (n_in = 2), PDG codes:
+ *   {-11, 11, -13, 13}            e+ e- -> mu+ mu- (s-channel photon and Z)
+ *   {21, 21, 6, -6 [, 21 ...]}    g g -> t t~ + 0..3 gluons
+ * Selects the process's compiled kernels on `device`, and determines the
+ * good helicities: every helicity configuration is evaluated in FP64 on 64
+ * RAMBO events (seed 1, sqrt(s) = 500 GeV for e+e- and 1500 GeV otherwise);
+ * a helicity is kept if its contribution is non-zero on at least one event.
+ * The process keeps no device memory.  Thread-safe.
+ * Errors: EINVAL (NULL pointer, n_in != 2, non-finite or non-positive
+ * couplings/masses), EUNSUPPORTED (other particles, wt != 0), EDEVICE. */
+int mgme_process_create(int n_in, int n_out, const int* pdg, const mgme_params* params, int device,
+                        mgme_process** out);
+
+/* Releases a process; NULL is accepted.  The caller must not use the process
+ * after this call, and must have finished (synchronised) its launches. */
+int mgme_process_destroy(mgme_process* proc);
+
+int mgme_process_info(const mgme_process* proc, mgme_info* out);
+
+/* The good-helicity list: codes[i] has bit (n_ext-1-leg) set when that leg
+ * has helicity +1.  `codes` holds at least n_hel entries; *n receives the
+ * number of good helicities. */
+int mgme_good_helicities(const mgme_process* proc, int* codes, int* n);
+
+/* The colour matrix of the trace basis as integer numerators num[n_colour^2]
+ * over the common denominator *den, and the basis: basis[s*k + j] is the
+ * j-th gluon leg of flow s (k gluons).  Either array pointer may be NULL. */
+int mgme_colour_matrix(const mgme_process* proc, long long* num, long long* den, int* basis);
+
+/* RAMBO flat phase space: events first_event .. first_event+nevt-1 of the
+ * Philox4x32-10 stream keyed by `seed`, written to d_mom (layout above, the
+ * two initial partons along +z and -z with energy sqrt_s/2) and the
+ * phase-space weights (with the (2 pi)^(4-3n) convention) to d_wgt[nevt]
+ * (d_wgt may be NULL).  Errors: EINVAL (sqrt_s not above the sum of the
+ * final-state masses, sizes), EDEVICE. */
+int mgme_rambo(const mgme_process* proc, double sqrt_s, unsigned long long seed,
+               unsigned long long first_event, long long nevt, long long ld, double* d_mom, double* d_wgt,
+               void* hip_stream);
+
+/* |M|^2 per event, summed over the good helicities and all colours and
+ * normalised by norm_factor, into d_me[nevt] (FP64 in every precision).
+ * Errors: EINVAL, EUNSUPPORTED (MGME_MIXED), EDEVICE. */
+int mgme_matrix_element(const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
+                        int precision, double* d_me, void* hip_stream);
+
+/* Per-helicity contributions of every one of the n_hel helicity
+ * configurations (not only the good ones), normalised like
+ * mgme_matrix_element: d_out[h*ldo + e], ldo >= nevt. */
+int mgme_matrix_element_per_helicity(const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
+                                     int precision, double* d_out, long long ldo, void* hip_stream);
+
+const char* mgme_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGME_H */

@@ -1,0 +1,181 @@
+"""mgme: tree-level |M|^2, summed over helicities and colours, on MI355X.
+
+Thin Python binding of libmgme.so (see include/mgme.h): argument marshalling
+only.  Device memory and streams come from PyTorch; every step of the
+computation runs in the library's HIP kernels.  Importing works without the
+library; the first call that needs it raises MgmeError if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgme.so")
+
+MGME_OK, MGME_EINVAL, MGME_EUNSUPPORTED, MGME_ENOMEM, MGME_EDEVICE = 0, -1, -2, -3, -4
+FP64, FP32, MIXED = 0, 1, 2
+
+PROCESSES = {
+    "ee_mumu": [-11, 11, -13, 13],
+    "gg_tt": [21, 21, 6, -6],
+    "gg_ttg": [21, 21, 6, -6, 21],
+    "gg_ttgg": [21, 21, 6, -6, 21, 21],
+    "gg_ttggg": [21, 21, 6, -6, 21, 21, 21],
+}
+
+DEFAULT_PARAMS = dict(alpha_s=0.118, alpha_em=1.0 / 132.5, sin2w=0.2222, mz=91.188, wz=2.441,
+                      mt=173.0, wt=0.0, z_enabled=1)
+
+# Entry points declared in include/mgme.h.
+EXPORTS = ["mgme_process_create", "mgme_process_destroy", "mgme_process_info", "mgme_good_helicities",
+           "mgme_colour_matrix", "mgme_rambo", "mgme_matrix_element", "mgme_matrix_element_per_helicity",
+           "mgme_last_error"]
+
+
+class MgmeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mgme error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha_s", ctypes.c_double), ("alpha_em", ctypes.c_double), ("sin2w", ctypes.c_double),
+                ("mz", ctypes.c_double), ("wz", ctypes.c_double), ("mt", ctypes.c_double),
+                ("wt", ctypes.c_double), ("z_enabled", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_ext", ctypes.c_int), ("n_diagrams", ctypes.c_int), ("n_amp_terms", ctypes.c_int),
+                ("n_colour", ctypes.c_int), ("n_hel", ctypes.c_int), ("n_good_hel", ctypes.c_int),
+                ("n_currents", ctypes.c_int), ("n_amp_vertices", ctypes.c_int),
+                ("norm_factor", ctypes.c_double), ("flops_per_hel", ctypes.c_double),
+                ("flops_per_event", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libmgme.so; raises MgmeError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MgmeError(MGME_EUNSUPPORTED, f"{LIB_PATH} is missing: run paper_2303_18244_amd.build first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, u64, dp = ctypes.c_void_p, ctypes.c_longlong, ctypes.c_ulonglong, ctypes.c_void_p
+        L.mgme_process_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(vp)]
+        L.mgme_process_destroy.argtypes = [vp]
+        L.mgme_process_info.argtypes = [vp, ctypes.POINTER(Info)]
+        L.mgme_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.mgme_colour_matrix.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
+                                         ctypes.POINTER(ctypes.c_int)]
+        L.mgme_rambo.argtypes = [vp, ctypes.c_double, u64, u64, i64, i64, dp, dp, vp]
+        L.mgme_matrix_element.argtypes = [vp, dp, i64, i64, ctypes.c_int, dp, vp]
+        L.mgme_matrix_element_per_helicity.argtypes = [vp, dp, i64, i64, ctypes.c_int, dp, i64, vp]
+        L.mgme_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "mgme_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != MGME_OK:
+        raise MgmeError(rc, lib().mgme_last_error().decode())
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Process:
+    """A compiled process on one GPU."""
+
+    def __init__(self, pdg: Sequence[int], device: int = 0, **params):
+        par = dict(DEFAULT_PARAMS)
+        par.update(params)
+        self.pdg = list(pdg)
+        self.device = device
+        self._h = ctypes.c_void_p()
+        arr = (ctypes.c_int * len(self.pdg))(*self.pdg)
+        _check(lib().mgme_process_create(2, len(self.pdg) - 2, arr, ctypes.byref(Params(**par)), device,
+                                         ctypes.byref(self._h)))
+        info = Info()
+        _check(lib().mgme_process_info(self._h, ctypes.byref(info)))
+        self.info = info.as_dict()
+        self.n_ext = info.n_ext
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib().mgme_process_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def good_helicities(self):
+        codes = (ctypes.c_int * (1 << self.n_ext))()
+        n = ctypes.c_int()
+        _check(lib().mgme_good_helicities(self._h, codes, ctypes.byref(n)))
+        return list(codes[: n.value])
+
+    def colour_matrix(self):
+        """(numerators [n][n], denominator, basis [n][k])."""
+        n = self.info["n_colour"]
+        k = sum(1 for x in self.pdg if x == 21)
+        num = (ctypes.c_longlong * (n * n))()
+        den = ctypes.c_longlong()
+        basis = (ctypes.c_int * max(1, n * k))()
+        _check(lib().mgme_colour_matrix(self._h, num, ctypes.byref(den), basis))
+        return ([list(num[r * n:(r + 1) * n]) for r in range(n)], den.value,
+                [list(basis[r * k:(r + 1) * k]) for r in range(n)])
+
+    def rambo(self, sqrt_s: float, seed: int, first_event: int, nevt: int, ld: Optional[int] = None,
+              mom=None, wgt=None, stream=None):
+        """RAMBO events on the device: returns (mom [n_ext, 4, ld] float64, wgt [nevt])."""
+        import torch
+        ld = nevt if ld is None else ld
+        dev = torch.device("cuda", self.device)
+        if mom is None:
+            mom = torch.empty((self.n_ext, 4, max(ld, 1)), dtype=torch.float64, device=dev)
+        if wgt is None:
+            wgt = torch.empty(max(nevt, 1), dtype=torch.float64, device=dev)
+        _check(lib().mgme_rambo(self._h, float(sqrt_s), int(seed), int(first_event), int(nevt), int(ld),
+                                mom.data_ptr(), wgt.data_ptr(), _stream_handle(stream)))
+        return mom, wgt
+
+    def matrix_element(self, mom, nevt: Optional[int] = None, precision: int = FP64, out=None, stream=None):
+        """|M|^2 per event for momenta mom [n_ext, 4, ld] (float64, on the device)."""
+        import torch
+        ld = mom.shape[-1]
+        nevt = ld if nevt is None else nevt
+        if mom.dtype != torch.float64 or not mom.is_contiguous() or mom.shape[:2] != (self.n_ext, 4):
+            raise MgmeError(MGME_EINVAL, "momenta must be a contiguous float64 tensor [n_ext, 4, ld]")
+        if out is None:
+            out = torch.empty(max(nevt, 1), dtype=torch.float64, device=mom.device)
+        _check(lib().mgme_matrix_element(self._h, mom.data_ptr(), int(nevt), int(ld), int(precision),
+                                         out.data_ptr(), _stream_handle(stream)))
+        return out[:nevt]
+
+    def matrix_element_per_helicity(self, mom, nevt: Optional[int] = None, precision: int = FP64, stream=None):
+        import torch
+        ld = mom.shape[-1]
+        nevt = ld if nevt is None else nevt
+        out = torch.empty((1 << self.n_ext, max(nevt, 1)), dtype=torch.float64, device=mom.device)
+        _check(lib().mgme_matrix_element_per_helicity(self._h, mom.data_ptr(), int(nevt), int(ld),
+                                                      int(precision), out.data_ptr(), int(out.shape[1]),
+                                                      _stream_handle(stream)))
+        return out[:, :nevt]

@@ -1,0 +1,367 @@
+// Device routines for helicity amplitudes on gfx950: external wavefunctions,
+// off-shell currents with their propagators and vertex contractions, in the
+// chiral representation, templated on the floating-point type T (double or
+// float).  Kinematic inputs (momenta, propagator denominators) are always
+// double; wavefunctions and vertex arithmetic are in T.
+//
+// The matrix element is built from Feynman diagrams and helicity amplitudes
+// (paper, section 1).  Conventions: metric (+,-,-,-); gamma^mu =
+// [[0, sigma^mu], [sigmabar^mu, 0]], sigma^mu = (1, s_k), sigmabar^mu =
+// (1, -s_k); upper spinor components are left-handed.  Every routine returns
+// the bare Lorentz structure: vertex couplings and the factors of i from
+// vertices and propagators are folded into one constant phase per diagram by
+// the process compiler.  Momenta passed to routines are flow-in momenta (the
+// momentum flowing from the current into the vertex that consumes it).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mgme {
+
+template <typename T> struct cx {
+  T re, im;
+};
+
+template <typename T> __device__ __forceinline__ cx<T> mk(T r, T i) { return cx<T>{r, i}; }
+template <typename T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <typename T> __device__ __forceinline__ cx<T> operator*(cx<T> a, cx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T> __device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T> __device__ __forceinline__ cx<T> conjg(cx<T> a) { return {a.re, -a.im}; }
+// i * a
+template <typename T> __device__ __forceinline__ cx<T> timesi(cx<T> a) { return {-a.im, a.re}; }
+
+// Four complex components: a spinor (ket column or bra row) or a
+// contravariant vector.
+template <typename T> struct wf {
+  cx<T> c[4];
+};
+
+// Minkowski product of two complex vectors (no conjugation).
+template <typename T> __device__ __forceinline__ cx<T> mdot(const wf<T>& a, const wf<T>& b) {
+  return a.c[0] * b.c[0] - a.c[1] * b.c[1] - a.c[2] * b.c[2] - a.c[3] * b.c[3];
+}
+// Minkowski product of a real vector with a complex vector.
+template <typename T> __device__ __forceinline__ cx<T> mdot(const T k[4], const wf<T>& a) {
+  return k[0] * a.c[0] - k[1] * a.c[1] - k[2] * a.c[2] - k[3] * a.c[3];
+}
+
+// ---------------------------------------------------------------- externals
+// Two-component helicity eigenvectors chi_+ and chi_- of sigma.p / |p|, with
+// the fixed phase chi_+ = (0,1), chi_- = (-1,0) for p along -z.
+__device__ __forceinline__ void helicity_basis(const double p[4], double chp[4], double chm[4]) {
+  const double px = p[1], py = p[2], pz = p[3];
+  const double pabs = sqrt(px * px + py * py + pz * pz);
+  if (px == 0.0 && py == 0.0 && pz < 0.0) {
+    chp[0] = 0; chp[1] = 0; chp[2] = 1; chp[3] = 0;
+    chm[0] = -1; chm[1] = 0; chm[2] = 0; chm[3] = 0;
+    return;
+  }
+  const double ppz = pz >= 0.0 ? pabs + pz : (px * px + py * py) / (pabs - pz);
+  const double nrm = 1.0 / sqrt(2.0 * pabs * ppz);
+  chp[0] = ppz * nrm; chp[1] = 0.0; chp[2] = px * nrm; chp[3] = py * nrm;    // (re0, im0, re1, im1)
+  chm[0] = -px * nrm; chm[1] = py * nrm; chm[2] = ppz * nrm; chm[3] = 0.0;
+}
+
+// sqrt(E + |p|) and sqrt(E - |p|) with the on-shell energy sqrt(|p|^2 + m^2).
+__device__ __forceinline__ void spinor_scales(const double p[4], double m, double& big, double& small) {
+  const double pabs = sqrt(p[1] * p[1] + p[2] * p[2] + p[3] * p[3]);
+  const double e = m == 0.0 ? pabs : sqrt(pabs * pabs + m * m);
+  big = sqrt(e + pabs);
+  small = m == 0.0 ? 0.0 : m / big;
+}
+
+// Ket spinor: u(p, lam) of an incoming fermion (anti = false) or v(p, lam)
+// of an outgoing antifermion (anti = true); lam = +-1 is the helicity.
+template <typename T>
+__device__ __forceinline__ wf<T> ext_ket(const double p[4], double m, int lam, bool anti) {
+  double chp[4], chm[4], big, small;
+  helicity_basis(p, chp, chm);
+  spinor_scales(p, m, big, small);
+  // u(+) = (small chi+, big chi+), u(-) = (big chi-, small chi-)
+  // v(+) = (-big chi-, small chi-), v(-) = (small chi+, -big chi+)
+  const bool plus_chi = anti ? (lam < 0) : (lam > 0);
+  const double* ch = plus_chi ? chp : chm;
+  double up, lo;
+  if (!anti) {
+    up = lam > 0 ? small : big;
+    lo = lam > 0 ? big : small;
+  } else {
+    up = lam > 0 ? -big : small;
+    lo = lam > 0 ? small : -big;
+  }
+  wf<T> w;
+  w.c[0] = mk<T>((T)(up * ch[0]), (T)(up * ch[1]));
+  w.c[1] = mk<T>((T)(up * ch[2]), (T)(up * ch[3]));
+  w.c[2] = mk<T>((T)(lo * ch[0]), (T)(lo * ch[1]));
+  w.c[3] = mk<T>((T)(lo * ch[2]), (T)(lo * ch[3]));
+  return w;
+}
+
+// Bra spinor (Dirac adjoint, psi^dagger gamma^0): ubar(p, lam) of an outgoing
+// fermion (anti = false) or vbar(p, lam) of an incoming antifermion.
+template <typename T>
+__device__ __forceinline__ wf<T> ext_bra(const double p[4], double m, int lam, bool anti) {
+  const wf<T> k = ext_ket<T>(p, m, lam, anti);
+  wf<T> b;
+  b.c[0] = conjg(k.c[2]);
+  b.c[1] = conjg(k.c[3]);
+  b.c[2] = conjg(k.c[0]);
+  b.c[3] = conjg(k.c[1]);
+  return b;
+}
+
+// Polarisation vector of a massless vector boson with helicity lam:
+// eps = (-lam e1 - i e2)/sqrt(2), e1 = (0, ct cp, ct sp, -st), e2 = (0, -sp, cp, 0);
+// complex conjugated for an outgoing boson.
+template <typename T>
+__device__ __forceinline__ wf<T> ext_vec(const double p[4], int lam, bool outgoing) {
+  const double px = p[1], py = p[2], pz = p[3];
+  const double pt = sqrt(px * px + py * py);
+  const double pabs = sqrt(px * px + py * py + pz * pz);
+  const double ct = pz / pabs, st = pt / pabs;
+  double cp = 1.0, sp = 0.0;
+  if (pt > 0.0) {
+    cp = px / pt;
+    sp = py / pt;
+  }
+  const double r2 = 0.70710678118654752440;
+  const double l = lam > 0 ? 1.0 : -1.0;
+  const double sgn = outgoing ? -1.0 : 1.0;  // conjugation flips the imaginary parts
+  wf<T> w;
+  w.c[0] = mk<T>((T)0, (T)0);
+  w.c[1] = mk<T>((T)(-l * ct * cp * r2), (T)(sgn * sp * r2));
+  w.c[2] = mk<T>((T)(-l * ct * sp * r2), (T)(-sgn * cp * r2));
+  w.c[3] = mk<T>((T)(l * st * r2), (T)0);
+  return w;
+}
+
+// ------------------------------------------------------------ Dirac blocks
+// V.sigma    = [[V0 - V3, -V1 + i V2], [-V1 - i V2, V0 + V3]]   (upper-right block of Vslash)
+// V.sigmabar = [[V0 + V3,  V1 - i V2], [ V1 + i V2, V0 - V3]]   (lower-left block)
+template <typename T> struct blocks2 {
+  cx<T> a00, a01, a10, a11;
+};
+template <typename T> __device__ __forceinline__ blocks2<T> vsigma(const wf<T>& V) {
+  return {V.c[0] - V.c[3], timesi(V.c[2]) - V.c[1], -V.c[1] - timesi(V.c[2]), V.c[0] + V.c[3]};
+}
+template <typename T> __device__ __forceinline__ blocks2<T> vsigmabar(const wf<T>& V) {
+  return {V.c[0] + V.c[3], V.c[1] - timesi(V.c[2]), V.c[1] + timesi(V.c[2]), V.c[0] - V.c[3]};
+}
+
+// ---------------------------------------------------------------- vertices
+// Amplitude bra . Vslash . ket  (quark-gluon vertex, vector coupling).
+template <typename T> __device__ __forceinline__ cx<T> ffv_amp(const wf<T>& bra, const wf<T>& ket, const wf<T>& V) {
+  const blocks2<T> A = vsigma(V), B = vsigmabar(V);
+  const cx<T> u0 = A.a00 * ket.c[2] + A.a01 * ket.c[3];
+  const cx<T> u1 = A.a10 * ket.c[2] + A.a11 * ket.c[3];
+  const cx<T> l0 = B.a00 * ket.c[0] + B.a01 * ket.c[1];
+  const cx<T> l1 = B.a10 * ket.c[0] + B.a11 * ket.c[1];
+  return bra.c[0] * u0 + bra.c[1] * u1 + bra.c[2] * l0 + bra.c[3] * l1;
+}
+
+// Off-shell ket: (qslash + m) Vslash ket * den, q the momentum along the fermion arrow.
+template <typename T>
+__device__ __forceinline__ wf<T> ket_prop(const wf<T>& ket, const wf<T>& V, const T q[4], T m, T den) {
+  const blocks2<T> A = vsigma(V), B = vsigmabar(V);
+  // x = Vslash ket
+  const cx<T> x0 = A.a00 * ket.c[2] + A.a01 * ket.c[3];
+  const cx<T> x1 = A.a10 * ket.c[2] + A.a11 * ket.c[3];
+  const cx<T> x2 = B.a00 * ket.c[0] + B.a01 * ket.c[1];
+  const cx<T> x3 = B.a10 * ket.c[0] + B.a11 * ket.c[1];
+  // y = (qslash + m) x, q real: q.sigma = [[q0-q3, -q1+iq2],[-q1-iq2, q0+q3]]
+  const T qa = q[0] - q[3], qb = q[0] + q[3];
+  const cx<T> qm = mk<T>(-q[1], q[2]);   // -q1 + i q2
+  const cx<T> qp = mk<T>(-q[1], -q[2]);  // -q1 - i q2
+  wf<T> y;
+  y.c[0] = den * (qa * x2 + qm * x3 + m * x0);
+  y.c[1] = den * (qp * x2 + qb * x3 + m * x1);
+  y.c[2] = den * (qb * x0 - qm * x1 + m * x2);
+  y.c[3] = den * (-qp * x0 + qa * x1 + m * x3);
+  return y;
+}
+
+// Off-shell bra: bra Vslash (qslash + m) * den with q = -P (P the flow-in
+// momentum of the new current).
+template <typename T>
+__device__ __forceinline__ wf<T> bra_prop(const wf<T>& bra, const wf<T>& V, const T P[4], T m, T den) {
+  const blocks2<T> A = vsigma(V), B = vsigmabar(V);
+  // x = bra Vslash (row): upper out = bra_lo B, lower out = bra_up A
+  const cx<T> x0 = bra.c[2] * B.a00 + bra.c[3] * B.a10;
+  const cx<T> x1 = bra.c[2] * B.a01 + bra.c[3] * B.a11;
+  const cx<T> x2 = bra.c[0] * A.a00 + bra.c[1] * A.a10;
+  const cx<T> x3 = bra.c[0] * A.a01 + bra.c[1] * A.a11;
+  // y = x (qslash + m) with q = -P: upper out = x_lo (q.sigmabar) + m x_up, lower out = x_up (q.sigma) + m x_lo
+  const T q0 = -P[0], q1 = -P[1], q2 = -P[2], q3 = -P[3];
+  const T qa = q0 - q3, qb = q0 + q3;
+  const cx<T> qm = mk<T>(-q1, q2);   // -q1 + i q2  (q.sigma off-diagonal 01)
+  const cx<T> qp = mk<T>(-q1, -q2);  // -q1 - i q2  (q.sigma off-diagonal 10)
+  // q.sigma = [[qa, qm], [qp, qb]], q.sigmabar = [[qb, -qm], [-qp, qa]]
+  wf<T> y;
+  y.c[0] = den * (qb * x2 - x3 * qp + m * x0);
+  y.c[1] = den * (-(x2 * qm) + qa * x3 + m * x1);
+  y.c[2] = den * (qa * x0 + x1 * qp + m * x2);
+  y.c[3] = den * (x0 * qm + qb * x1 + m * x3);
+  return y;
+}
+
+// Vector current bra gamma^mu ket * den (contravariant index).
+template <typename T> __device__ __forceinline__ wf<T> ffv_vec(const wf<T>& b, const wf<T>& k, T den) {
+  wf<T> J;
+  J.c[0] = den * (b.c[0] * k.c[2] + b.c[1] * k.c[3] + b.c[2] * k.c[0] + b.c[3] * k.c[1]);
+  J.c[1] = den * (b.c[0] * k.c[3] + b.c[1] * k.c[2] - b.c[2] * k.c[1] - b.c[3] * k.c[0]);
+  J.c[2] = den * timesi(b.c[1] * k.c[2] - b.c[0] * k.c[3] - b.c[3] * k.c[0] + b.c[2] * k.c[1]);
+  J.c[3] = den * (b.c[0] * k.c[2] - b.c[1] * k.c[3] - b.c[2] * k.c[0] + b.c[3] * k.c[1]);
+  return J;
+}
+
+// Chiral vector current bra gamma^mu (gL PL + gR PR) ket (no propagator).
+template <typename T>
+__device__ __forceinline__ wf<T> ffv_vec_chiral(const wf<T>& b, const wf<T>& k, T gL, T gR) {
+  // right-handed part: bra_up sigma^mu ket_lo; left-handed part: bra_lo sigmabar^mu ket_up
+  const cx<T> r0 = b.c[0] * k.c[2] + b.c[1] * k.c[3];
+  const cx<T> l0 = b.c[2] * k.c[0] + b.c[3] * k.c[1];
+  const cx<T> r1 = b.c[0] * k.c[3] + b.c[1] * k.c[2];
+  const cx<T> l1 = b.c[2] * k.c[1] + b.c[3] * k.c[0];
+  const cx<T> r2 = b.c[1] * k.c[2] - b.c[0] * k.c[3];
+  const cx<T> l2 = b.c[2] * k.c[1] - b.c[3] * k.c[0];
+  const cx<T> r3 = b.c[0] * k.c[2] - b.c[1] * k.c[3];
+  const cx<T> l3 = b.c[3] * k.c[1] - b.c[2] * k.c[0];
+  wf<T> J;
+  J.c[0] = gR * r0 + gL * l0;
+  J.c[1] = gR * r1 - gL * l1;
+  J.c[2] = timesi(gR * r2 + gL * l2);
+  J.c[3] = gR * r3 + gL * l3;
+  return J;
+}
+
+// Three-gluon vertex with leg 3 off shell, all momenta flowing in (k3 = -k1-k2):
+// [(V1.V2)(k1-k2) + V2 ((k1+2k2).V1) - V1 ((2k1+k2).V2)] * den
+template <typename T>
+__device__ __forceinline__ wf<T> vvv_vec(const wf<T>& V1, const T k1[4], const wf<T>& V2, const T k2[4], T den) {
+  T d[4], a[4], b[4];
+  for (int mu = 0; mu < 4; ++mu) {
+    d[mu] = k1[mu] - k2[mu];
+    a[mu] = k1[mu] + 2 * k2[mu];
+    b[mu] = 2 * k1[mu] + k2[mu];
+  }
+  const cx<T> v12 = mdot(V1, V2);
+  const cx<T> s1 = mdot(a, V1);
+  const cx<T> s2 = mdot(b, V2);
+  wf<T> W;
+  for (int mu = 0; mu < 4; ++mu) W.c[mu] = den * (d[mu] * v12 + V2.c[mu] * s1 - V1.c[mu] * s2);
+  return W;
+}
+
+// Three-gluon vertex amplitude, all momenta flowing in.
+template <typename T>
+__device__ __forceinline__ cx<T> vvv_amp(const wf<T>& V1, const T k1[4], const wf<T>& V2, const T k2[4],
+                                         const wf<T>& V3, const T k3[4]) {
+  T d12[4], d23[4], d31[4];
+  for (int mu = 0; mu < 4; ++mu) {
+    d12[mu] = k1[mu] - k2[mu];
+    d23[mu] = k2[mu] - k3[mu];
+    d31[mu] = k3[mu] - k1[mu];
+  }
+  return mdot(V1, V2) * mdot(d12, V3) + mdot(V2, V3) * mdot(d23, V1) + mdot(V3, V1) * mdot(d31, V2);
+}
+
+// Four-gluon vertex, one of its three colour structures, leg 4 off shell.
+template <typename T, int S>
+__device__ __forceinline__ wf<T> vvvv_vec(const wf<T>& V1, const wf<T>& V2, const wf<T>& V3, T den) {
+  wf<T> W;
+  if (S == 0) {  // (V1.V3) V2 - (V2.V3) V1
+    const cx<T> a = den * mdot(V1, V3), b = den * mdot(V2, V3);
+    for (int mu = 0; mu < 4; ++mu) W.c[mu] = a * V2.c[mu] - b * V1.c[mu];
+  } else if (S == 1) {  // (V1.V2) V3 - (V2.V3) V1
+    const cx<T> a = den * mdot(V1, V2), b = den * mdot(V2, V3);
+    for (int mu = 0; mu < 4; ++mu) W.c[mu] = a * V3.c[mu] - b * V1.c[mu];
+  } else {  // (V1.V2) V3 - (V1.V3) V2
+    const cx<T> a = den * mdot(V1, V2), b = den * mdot(V1, V3);
+    for (int mu = 0; mu < 4; ++mu) W.c[mu] = a * V3.c[mu] - b * V2.c[mu];
+  }
+  return W;
+}
+
+template <typename T, int S>
+__device__ __forceinline__ cx<T> vvvv_amp(const wf<T>& V1, const wf<T>& V2, const wf<T>& V3, const wf<T>& V4) {
+  if (S == 0) return mdot(V1, V3) * mdot(V2, V4) - mdot(V1, V4) * mdot(V2, V3);
+  if (S == 1) return mdot(V1, V2) * mdot(V3, V4) - mdot(V1, V4) * mdot(V2, V3);
+  return mdot(V1, V2) * mdot(V3, V4) - mdot(V1, V3) * mdot(V2, V4);
+}
+
+// Adds c * a to J for a Gaussian-integer c in {+-1, +-i} (or small integers).
+template <typename T> __device__ __forceinline__ void acc(cx<T>& J, cx<T> a, int cre, int cim) {
+  if (cim == 0) {
+    if (cre == 1) J = J + a;
+    else if (cre == -1) J = J - a;
+    else J = J + (T)cre * a;
+  } else if (cre == 0) {
+    if (cim == 1) J = J + timesi(a);
+    else if (cim == -1) J = J - timesi(a);
+    else J = J + (T)cim * timesi(a);
+  } else {
+    J = J + (T)cre * a + (T)cim * timesi(a);
+  }
+}
+
+// ------------------------------------------------------- register control
+// The straight-line helicity body is evaluated in the order the process
+// compiler chose to keep few wavefunctions alive.  An empty volatile asm
+// statement gives a value a new identity the compiler cannot see through, so
+// each routine call works on fresh copies of its inputs: the compiler can
+// neither merge the arithmetic of two calls (which would stretch live ranges
+// across the whole body) nor hoist a call above the previous one.
+__device__ __forceinline__ double fresh(double x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+__device__ __forceinline__ float fresh(float x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+template <typename T> __device__ __forceinline__ wf<T> fresh(const wf<T>& w) {
+  wf<T> r = w;
+  asm volatile("" : "+v"(r.c[0].re), "+v"(r.c[0].im), "+v"(r.c[1].re), "+v"(r.c[1].im), "+v"(r.c[2].re),
+               "+v"(r.c[2].im), "+v"(r.c[3].re), "+v"(r.c[3].im));
+  return r;
+}
+// External polarisation vectors have a vanishing time component and a real
+// z component; keep those constants visible.
+template <typename T> __device__ __forceinline__ wf<T> fresh_pol(const wf<T>& w) {
+  wf<T> r = w;
+  asm volatile("" : "+v"(r.c[1].re), "+v"(r.c[1].im), "+v"(r.c[2].re), "+v"(r.c[2].im), "+v"(r.c[3].re));
+  r.c[0] = mk<T>((T)0, (T)0);
+  r.c[3].im = (T)0;
+  return r;
+}
+
+// Flow-in momentum of the legs in MASK (incoming legs in INMASK count with +,
+// outgoing ones with -), summed from fresh copies of the external momenta.
+template <unsigned MASK, unsigned INMASK, int NEXT>
+__device__ __forceinline__ void flow_momentum(double out[4], const double (&q)[NEXT][4]) {
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NEXT; ++i)
+      if (MASK & (1u << i)) {
+        const double x = fresh(q[i][mu]);
+        acc = (INMASK & (1u << i)) ? acc + x : acc - x;
+      }
+    out[mu] = acc;
+  }
+}
+
+template <typename T> __device__ __forceinline__ void to_t(T out[4], const double in[4]) {
+  out[0] = (T)in[0]; out[1] = (T)in[1]; out[2] = (T)in[2]; out[3] = (T)in[3];
+}
+
+// 1 / (P^2 - m^2) in double precision.
+__device__ __forceinline__ double inv_virt(const double P[4], double m) {
+  return 1.0 / (P[0] * P[0] - P[1] * P[1] - P[2] * P[2] - P[3] * P[3] - m * m);
+}
+
+}  // namespace mgme

@@ -1,0 +1,31 @@
+// Arguments shared by the generated matrix-element kernels and the runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#ifndef MGME_ME_BLOCK
+#define MGME_ME_BLOCK 128
+#endif
+
+#define MGME_MAX_HEL 128
+
+namespace mgme {
+
+// Passed by value as a kernel argument, so that the helicity list is read
+// through the scalar unit: every lane of a wave evaluates the same helicity.
+struct MeArgs {
+  double mt;        // top-quark mass (GeV)
+  double factor;    // gs^(2k) / (spin-colour average * identical-particle factor * colour denominator)
+  double ee_qq;     // e^2 Q_e Q_mu (photon exchange)
+  double ee_zz;     // e^2 / (sw^2 cw^2) (Z exchange)
+  double ee_gl;     // T3 - Q sw^2 of the charged leptons
+  double ee_gr;     // -Q sw^2
+  double mz, wz;
+  int z_enabled;
+  int nhel;                 // helicities to sum
+  int hel[MGME_MAX_HEL];    // helicity codes: bit (n_ext-1-leg) set for helicity +1
+};
+
+using LaunchFn = hipError_t (*)(int prec, int per_hel, const double* mom, long long nevt, long long ld,
+                                const MeArgs* args, double* out, long long ldo, hipStream_t stream);
+
+}  // namespace mgme

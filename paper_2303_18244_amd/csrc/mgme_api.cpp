@@ -1,0 +1,299 @@
+// C-ABI runtime of libmgme.so: process creation (process selection,
+// couplings, good-helicity calibration), argument validation and kernel
+// launches.  See include/mgme.h for the contract of every entry point.
+#include "../../include/mgme.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "me_kernel.h"
+#include "rambo.h"
+#include "registry.h"
+
+struct mgme_process {
+  const mgme::ProcEntry* entry;
+  int device;
+  mgme::MeArgs args;      // args.hel holds the good helicities
+  int n_out;
+  double mass_out[6];
+  double norm_factor;
+  double gs;
+};
+
+namespace {
+
+thread_local std::string g_error;
+
+int fail(int code, const std::string& msg) {
+  g_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(MGME_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Reports a pending asynchronous error of an earlier launch.
+int check_pending(const char* where) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, where);
+  return MGME_OK;
+}
+
+int select_device(int device) {
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != device) {
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  }
+  return MGME_OK;
+}
+
+double massless_rambo_weight(int n, double sqrt_s) {
+  const double pi = 3.141592653589793238462643383279502884;
+  double f1 = 1.0, f2 = 1.0;
+  for (int k = 2; k <= n - 1; ++k) f1 *= k;
+  for (int k = 2; k <= n - 2; ++k) f2 *= k;
+  const double s = sqrt_s * sqrt_s;
+  return std::pow(pi / 2.0, n - 1) * std::pow(s, n - 2) / (f1 * f2) * std::pow(2.0 * pi, 4 - 3 * n);
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int launch_rambo_checked(const mgme_process* p, double sqrt_s, unsigned long long seed, unsigned long long first,
+                         long long nevt, long long ld, double* d_mom, double* d_wgt, hipStream_t stream) {
+  mgme::RamboArgs a{};
+  a.sqrt_s = sqrt_s;
+  a.massless_weight = massless_rambo_weight(p->n_out, sqrt_s);
+  double msum = 0.0;
+  for (int i = 0; i < p->n_out; ++i) {
+    a.mass[i] = p->mass_out[i];
+    msum += p->mass_out[i];
+    if (p->mass_out[i] != 0.0) a.massive = 1;
+  }
+  if (!(sqrt_s > msum) || !std::isfinite(sqrt_s)) return fail(MGME_EINVAL, "sqrt_s must exceed the final-state masses");
+  a.seed = seed;
+  a.first_event = first;
+  const hipError_t e = mgme::launch_rambo(a, p->n_out, nevt, ld, d_mom, d_wgt, stream);
+  if (e != hipSuccess) return hip_fail(e, "rambo launch");
+  return MGME_OK;
+}
+
+// Good helicities: every helicity in FP64 on 64 RAMBO events; keep those with
+// a non-zero contribution on at least one event.
+int calibrate(mgme_process* p) {
+  const int n_ext = p->entry->n_ext;
+  const int nhel = 1 << n_ext;
+  const long long nev = 64;
+  double *d_mom = nullptr, *d_out = nullptr;
+  hipError_t e = hipMalloc(&d_mom, sizeof(double) * 4 * n_ext * nev);
+  if (e != hipSuccess) return fail(MGME_ENOMEM, "calibration buffer");
+  e = hipMalloc(&d_out, sizeof(double) * nhel * nev);
+  if (e != hipSuccess) {
+    (void)hipFree(d_mom);
+    return fail(MGME_ENOMEM, "calibration buffer");
+  }
+  int rc = MGME_OK;
+  const double sqrt_s = p->entry->kind == mgme::KIND_EE ? 500.0 : 1500.0;
+  std::vector<double> h((size_t)nhel * nev);
+  mgme::MeArgs all = p->args;
+  all.nhel = nhel;
+  for (int i = 0; i < nhel; ++i) all.hel[i] = i;
+  rc = launch_rambo_checked(p, sqrt_s, 1ull, 0ull, nev, nev, d_mom, nullptr, nullptr);
+  if (rc == MGME_OK) {
+    e = p->entry->launch(0, 1, d_mom, nev, nev, &all, d_out, nev, nullptr);
+    if (e != hipSuccess) rc = hip_fail(e, "calibration launch");
+  }
+  if (rc == MGME_OK) {
+    e = hipMemcpy(h.data(), d_out, sizeof(double) * nhel * nev, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) rc = hip_fail(e, "calibration copy");
+  }
+  (void)hipFree(d_mom);
+  (void)hipFree(d_out);
+  if (rc != MGME_OK) return rc;
+  int ng = 0;
+  for (int hh = 0; hh < nhel; ++hh) {
+    bool good = false;
+    for (long long ev = 0; ev < nev; ++ev)
+      if (h[(size_t)hh * nev + ev] != 0.0) good = true;
+    if (good) p->args.hel[ng++] = hh;
+  }
+  p->args.nhel = ng;
+  return MGME_OK;
+}
+
+const mgme::ProcEntry* find_process(int n_ext, const int* pdg) {
+  for (int i = 0; i < mgme::kNumProcesses; ++i) {
+    const mgme::ProcEntry& e = mgme::kProcesses[i];
+    if (e.n_ext != n_ext) continue;
+    bool same = true;
+    for (int k = 0; k < n_ext; ++k)
+      if (e.pdg[k] != pdg[k]) same = false;
+    if (same) return &e;
+  }
+  return nullptr;
+}
+
+int check_batch(const mgme_process* proc, const void* a, const void* b, long long nevt, long long ld) {
+  if (!proc) return fail(MGME_EINVAL, "process is NULL");
+  if (nevt < 0) return fail(MGME_EINVAL, "nevt < 0");
+  if (ld < nevt) return fail(MGME_EINVAL, "ld < nevt");
+  if (nevt > 0 && (!a || !b)) return fail(MGME_EINVAL, "NULL device pointer");
+  if (nevt > (1ll << 31) * 64) return fail(MGME_EINVAL, "nevt too large");
+  return MGME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mgme_last_error(void) { return g_error.c_str(); }
+
+int mgme_process_create(int n_in, int n_out, const int* pdg, const mgme_params* params, int device,
+                        mgme_process** out) {
+  if (!out) return fail(MGME_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!pdg || !params) return fail(MGME_EINVAL, "NULL argument");
+  if (n_in != 2 || n_out < 2 || n_out > 5) return fail(MGME_EINVAL, "need 2 initial and 2..5 final particles");
+  const mgme::ProcEntry* entry = find_process(n_in + n_out, pdg);
+  if (!entry) return fail(MGME_EUNSUPPORTED, "process not supported");
+  const mgme_params& P = *params;
+  if (P.wt != 0.0) return fail(MGME_EUNSUPPORTED, "a non-zero top width is not supported");
+  if (entry->kind == mgme::KIND_QCD && !(finite_pos(P.alpha_s) && finite_pos(P.mt)))
+    return fail(MGME_EINVAL, "alpha_s and mt must be positive and finite");
+  if (entry->kind == mgme::KIND_EE &&
+      !(finite_pos(P.alpha_em) && finite_pos(P.sin2w) && P.sin2w < 1.0 && finite_pos(P.mz) &&
+        std::isfinite(P.wz) && P.wz >= 0.0))
+    return fail(MGME_EINVAL, "electroweak parameters out of range");
+  int ndev = 0;
+  hipError_t he = hipGetDeviceCount(&ndev);
+  if (he != hipSuccess) return hip_fail(he, "hipGetDeviceCount");
+  if (device < 0 || device >= ndev) return fail(MGME_EINVAL, "no such device");
+  int rc = select_device(device);
+  if (rc != MGME_OK) return rc;
+
+  mgme_process* p = new (std::nothrow) mgme_process();
+  if (!p) return fail(MGME_ENOMEM, "host allocation");
+  p->entry = entry;
+  p->device = device;
+  p->n_out = n_out;
+  const double pi = 3.141592653589793238462643383279502884;
+  for (int i = 0; i < n_out; ++i) p->mass_out[i] = std::abs(pdg[2 + i]) == 6 ? P.mt : 0.0;
+  std::memset(&p->args, 0, sizeof p->args);
+  p->args.mt = P.mt;
+  p->norm_factor = 1.0 / ((double)entry->spin_colour_avg * (double)entry->ident);
+  if (entry->kind == mgme::KIND_QCD) {
+    p->gs = std::sqrt(4.0 * pi * P.alpha_s);
+    p->args.factor = std::pow(p->gs, entry->gs_power) * p->norm_factor / (double)entry->cden;
+  } else {
+    const double e2 = 4.0 * pi * P.alpha_em;
+    const double sw2 = P.sin2w, cw2 = 1.0 - sw2;
+    p->args.factor = p->norm_factor;
+    p->args.ee_qq = e2;  // Q_e Q_mu = 1
+    p->args.ee_zz = e2 / (sw2 * cw2);
+    p->args.ee_gl = -0.5 + sw2;
+    p->args.ee_gr = sw2;
+    p->args.mz = P.mz;
+    p->args.wz = P.wz;
+    p->args.z_enabled = P.z_enabled ? 1 : 0;
+  }
+  rc = calibrate(p);
+  if (rc != MGME_OK) {
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return MGME_OK;
+}
+
+int mgme_process_destroy(mgme_process* proc) {
+  delete proc;
+  return MGME_OK;
+}
+
+int mgme_process_info(const mgme_process* proc, mgme_info* out) {
+  if (!proc || !out) return fail(MGME_EINVAL, "NULL argument");
+  const mgme::ProcEntry& e = *proc->entry;
+  out->n_ext = e.n_ext;
+  out->n_diagrams = e.n_diagrams;
+  out->n_amp_terms = e.n_terms;
+  out->n_colour = e.n_colour;
+  out->n_hel = 1 << e.n_ext;
+  out->n_good_hel = proc->args.nhel;
+  out->n_currents = e.n_currents;
+  out->n_amp_vertices = e.n_amps;
+  out->norm_factor = proc->norm_factor;
+  out->flops_per_hel = e.flops_per_hel;
+  out->flops_per_event = e.flops_per_event;
+  return MGME_OK;
+}
+
+int mgme_good_helicities(const mgme_process* proc, int* codes, int* n) {
+  if (!proc || !codes || !n) return fail(MGME_EINVAL, "NULL argument");
+  for (int i = 0; i < proc->args.nhel; ++i) codes[i] = proc->args.hel[i];
+  *n = proc->args.nhel;
+  return MGME_OK;
+}
+
+int mgme_colour_matrix(const mgme_process* proc, long long* num, long long* den, int* basis) {
+  if (!proc) return fail(MGME_EINVAL, "NULL argument");
+  const mgme::ProcEntry& e = *proc->entry;
+  if (num)
+    for (int i = 0; i < e.n_colour * e.n_colour; ++i) num[i] = e.colour_num[i];
+  if (den) *den = e.cden;
+  if (basis)
+    for (int i = 0; i < e.n_colour * e.n_gluons; ++i) basis[i] = e.basis[i];
+  return MGME_OK;
+}
+
+int mgme_rambo(const mgme_process* proc, double sqrt_s, unsigned long long seed, unsigned long long first_event,
+               long long nevt, long long ld, double* d_mom, double* d_wgt, void* hip_stream) {
+  int rc = check_batch(proc, d_mom, d_mom, nevt, ld);
+  if (rc != MGME_OK) return rc;
+  if ((rc = check_pending("mgme_rambo")) != MGME_OK) return rc;
+  if (nevt == 0) return MGME_OK;
+  if ((rc = select_device(proc->device)) != MGME_OK) return rc;
+  return launch_rambo_checked(proc, sqrt_s, seed, first_event, nevt, ld, d_mom, d_wgt, (hipStream_t)hip_stream);
+}
+
+int mgme_matrix_element(const mgme_process* proc, const double* d_mom, long long nevt, long long ld, int precision,
+                        double* d_me, void* hip_stream) {
+  int rc = check_batch(proc, d_mom, d_me, nevt, ld);
+  if (rc != MGME_OK) return rc;
+  if (precision == MGME_MIXED) return fail(MGME_EUNSUPPORTED, "mixed precision is not available");
+  if (precision != MGME_FP64 && precision != MGME_FP32) return fail(MGME_EINVAL, "unknown precision");
+  if ((rc = check_pending("mgme_matrix_element")) != MGME_OK) return rc;
+  if (nevt == 0) return MGME_OK;
+  if ((rc = select_device(proc->device)) != MGME_OK) return rc;
+  const hipError_t e =
+      proc->entry->launch(precision, 0, d_mom, nevt, ld, &proc->args, d_me, 0, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "matrix element launch");
+  return MGME_OK;
+}
+
+int mgme_matrix_element_per_helicity(const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
+                                     int precision, double* d_out, long long ldo, void* hip_stream) {
+  int rc = check_batch(proc, d_mom, d_out, nevt, ld);
+  if (rc != MGME_OK) return rc;
+  if (ldo < nevt) return fail(MGME_EINVAL, "ldo < nevt");
+  if (precision != MGME_FP64 && precision != MGME_FP32) return fail(MGME_EINVAL, "unknown precision");
+  if ((rc = check_pending("mgme_matrix_element_per_helicity")) != MGME_OK) return rc;
+  if (nevt == 0) return MGME_OK;
+  if ((rc = select_device(proc->device)) != MGME_OK) return rc;
+  mgme::MeArgs all = proc->args;
+  all.nhel = 1 << proc->entry->n_ext;
+  for (int i = 0; i < all.nhel; ++i) all.hel[i] = i;
+  const hipError_t e = proc->entry->launch(precision, 1, d_mom, nevt, ld, &all, d_out, ldo, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "matrix element launch");
+  return MGME_OK;
+}
+
+}  // extern "C"
