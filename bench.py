@@ -1,0 +1,149 @@
+"""Throughput of the matrix-element hot path on one MI355X.
+
+One step = one pass of the whole hot path over one batch of synthetic
+events: RAMBO phase space (Philox4x32-10 counters, flat, no cuts) written to
+device memory, then |M|^2 summed over the good helicities and all colours.
+The default workload is g g -> t t~ g g at sqrt(s) = 1500 GeV, 524288
+events per batch, FP64 (the paper's standalone double-precision
+configuration with a grid of 524288 events).
+
+Prints one JSON line.  `value` is events per second over the timed steps;
+`roofline` is measured live with HIP events around every matrix-element
+launch on the stream it runs on; `cpu_baseline` times the oracle on a
+bounded sample of the same events on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOADS = {
+    # name: (pdg key, events per batch, sqrt(s) GeV)
+    "gg_ttgg": ("gg_ttgg", 524288, 1500.0),
+    "gg_ttggg": ("gg_ttggg", 65536, 1500.0),
+    "gg_tt": ("gg_tt", 524288, 1500.0),
+    "ee_mumu": ("ee_mumu", 16384, 500.0),
+}
+SEED = 230318244
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 78.6   # the same lanes without packed FP32 instructions
+# The paper's standalone CUDA throughput on one V100 for this workload
+# (g g -> t t~ g g, double, grid 524288): 4.21E5 MEs/s.
+PAPER_MES = {("gg_ttgg", 0): 4.21e5, ("gg_ttgg", 1): 8.77e5}
+
+
+def cpu_baseline(name: str, n_events: int, mom_host, seconds: float = 12.0):
+    """Oracle MEs/s on the host cores, on the leading events of the batch."""
+    import numpy as np
+
+    import oracle
+
+    P = oracle.Process(oracle.PROCESSES[name])
+    threads = max(1, min(16, os.cpu_count() or 1))
+    # size the sample from a short probe so that it takes about `seconds`
+    probe = mom_host[: 2 * threads]
+    t0 = time.perf_counter()
+    P.me(probe, nthreads=threads)
+    per_event = (time.perf_counter() - t0) / len(probe)
+    n = int(min(len(mom_host), max(len(probe), seconds / max(per_event, 1e-9))))
+    t0 = time.perf_counter()
+    P.me(mom_host[:n], nthreads=threads)
+    wall = time.perf_counter() - t0
+    return {"value": n / wall, "unit": "MEs/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of the {n_events} benchmark events, all helicities, FP64, "
+                      f"{threads} threads, {wall:.1f} s wall"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="gg_ttgg", choices=list(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (events are independent, "
+              f"so N GPUs would each run this batch on their own share).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2303_18244_amd as M
+
+    key, nevt, sqrt_s = WORKLOADS[a.workload]
+    prec = M.FP64 if a.precision == "fp64" else M.FP32
+    P = M.Process(M.PROCESSES[key])
+    info = P.info
+    dev = torch.device("cuda", 0)
+    mom = torch.empty((P.n_ext, 4, nevt), dtype=torch.float64, device=dev)
+    wgt = torch.empty(nevt, dtype=torch.float64, device=dev)
+    me = torch.empty(nevt, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(i, ev=None):
+        P.rambo(sqrt_s, SEED, i * nevt, nevt, mom=mom, wgt=wgt)
+        if ev is not None:
+            ev[0].record(stream)
+        P.matrix_element(mom, precision=prec, out=me)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for i in range(a.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        step(a.warmup + i, evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    me_ms = sum(e0.elapsed_time(e1) for e0, e1 in evs) / a.steps
+    ms_per_step = wall * 1e3 / a.steps
+    value = nevt / (ms_per_step * 1e-3)
+    ngood = info["n_good_hel"]
+    flops = (info["flops_per_hel"] * ngood + info["flops_per_event"]) * nevt
+    achieved = flops / (me_ms * 1e-3) * 1e-12
+    peak = FP64_VALU_PEAK_TFLOPS if prec == M.FP64 else FP32_VALU_PEAK_TFLOPS
+    assert bool(torch.isfinite(me).all()), "non-finite matrix element"
+
+    result = {
+        "metric": "MEs/s (tree-level |M|^2 summed over helicities and colours, RAMBO + ME per batch)",
+        "value": value,
+        "unit": "MEs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": (value / PAPER_MES[(key, prec)]) if (key, prec) in PAPER_MES else None,
+        "dtype": "f64" if prec == M.FP64 else "f32",
+        "data": "synthetic (RAMBO flat phase space, Philox seed 230318244)",
+        "config": {"workload": key, "events_per_batch": nevt, "sqrt_s_gev": sqrt_s,
+                   "precision": a.precision, "good_helicities": ngood, "diagrams": info["n_diagrams"],
+                   "colour_flows": info["n_colour"]},
+        "me_only": {"ms_per_launch": me_ms, "mes_per_s": nevt / (me_ms * 1e-3)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": f"me_kernel<{'double' if prec == M.FP64 else 'float'}> ({key})",
+                     "flops_per_launch": flops},
+    }
+    if not a.no_cpu_baseline:
+        host = mom.cpu().numpy().transpose(2, 0, 1)
+        host = np.ascontiguousarray(host[:65536])
+        result["cpu_baseline"] = cpu_baseline(key, nevt, host)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,242 @@
+"""GPU parity of the HIP path (through the C ABI) against the oracle.
+
+Tolerances: FP64 |M|^2 per event within 1e-12 relative (an event outside it
+is re-evaluated by the long-double oracle and must be within 1e-12 of that);
+FP32 diagrams: the batch mean and the per-event median within 1e-5
+relative (the paper's cross-section criterion for reduced precision),
+per-event p99 and maximum printed.  RAMBO momenta within 1e-12 sqrt(s):
+the conformal boost amplifies rounding for nearly collinear pairs, so host
+and device libm results agree only to that level.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+SEED = 230318244
+NTHREADS = max(1, min(16, os.cpu_count() or 1))
+
+# name -> (events checked against the oracle, full configuration size, sqrt(s))
+CASES = {
+    "ee_mumu": (16384, 16384, 500.0),
+    "gg_tt": (8192, 524288, 1500.0),
+    "gg_ttg": (2048, 65536, 1500.0),
+    "gg_ttgg": (389, 524288, 1500.0),
+    "gg_ttggg": (67, 65536, 1500.0),
+}
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def lib_procs():
+    _torch()
+    import paper_2303_18244_amd as M
+
+    out = {}
+    for name, pdg in M.PROCESSES.items():
+        try:
+            out[name] = M.Process(pdg)
+        except M.MgmeError as e:
+            if e.code == M.MGME_EUNSUPPORTED:
+                continue
+            raise
+    return out
+
+
+@pytest.fixture(scope="module")
+def oracle_procs(oracle_mod):
+    return {name: oracle_mod.Process(pdg) for name, pdg in oracle_mod.PROCESSES.items()}
+
+
+def _proc(lib_procs, name):
+    if name not in lib_procs:
+        pytest.skip(f"{name} not compiled into libmgme.so")
+    return lib_procs[name]
+
+
+def _host(mom, nevt):
+    """[n_ext, 4, ld] device tensor -> [nevt, n_ext, 4] host array."""
+    return mom[:, :, :nevt].cpu().numpy().transpose(2, 0, 1).copy()
+
+
+def _masses(pdg):
+    return [173.0 if abs(x) == 6 else 0.0 for x in pdg[2:]]
+
+
+def _check_fp64(gpu, mom_host, oproc, tol=1e-12):
+    ref = oproc.me(mom_host, nthreads=NTHREADS)
+    rel = np.abs(gpu / ref - 1.0)
+    bad = np.nonzero(rel > tol)[0]
+    if len(bad):
+        ld = oproc.me(mom_host[bad], precision=1, nthreads=NTHREADS)
+        rel_ld = np.abs(gpu[bad] / ld - 1.0)
+        assert np.all(rel_ld <= tol), (bad[:10], rel[bad][:10], rel_ld[:10])
+    return rel
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rambo_matches_oracle(lib_procs, oracle_mod, name):
+    torch = _torch()
+    P = _proc(lib_procs, name)
+    n, _, sq = CASES[name]
+    n = min(n, 4096)
+    mom, wgt = P.rambo(sq, SEED, 0, n)
+    torch.cuda.synchronize()
+    om, ow = oracle_mod.rambo(_masses(P.pdg), sq, SEED, 0, n)
+    dp = np.abs(_host(mom, n) - om).max()
+    assert dp <= 1e-12 * sq, dp
+    np.testing.assert_allclose(wgt.cpu().numpy()[:n], ow, rtol=1e-11)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_matches_oracle(lib_procs, oracle_procs, name):
+    torch = _torch()
+    P = _proc(lib_procs, name)
+    n, _, sq = CASES[name]
+    mom, _ = P.rambo(sq, SEED, 0, n)
+    me = P.matrix_element(mom).cpu().numpy()
+    rel = _check_fp64(me, _host(mom, n), oracle_procs[name])
+    print(f"{name} FP64 vs oracle on {n} events: max rel {rel.max():.2e}, median {np.median(rel):.2e}")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp32_accuracy(lib_procs, oracle_procs, name):
+    torch = _torch()
+    P = _proc(lib_procs, name)
+    n, _, sq = CASES[name]
+    mom, _ = P.rambo(sq, SEED, 0, n)
+    me = P.matrix_element(mom, precision=1).cpu().numpy()
+    ref = oracle_procs[name].me(_host(mom, n), nthreads=NTHREADS)
+    rel = np.abs(me / ref - 1.0)
+    mean_rel = abs(me.mean() / ref.mean() - 1.0)
+    print(f"{name} FP32 vs oracle on {n} events: batch-mean {mean_rel:.2e}, median {np.median(rel):.2e}, "
+          f"p99 {np.quantile(rel, 0.99):.2e}, max {rel.max():.2e}")
+    assert mean_rel <= 1e-5
+    assert np.median(rel) <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_size_sampled(lib_procs, oracle_procs, name):
+    """The configuration's full batch in one launch: sampled events against the
+    oracle, and the leading events bitwise equal to a small batch (no
+    dependence on the batch size or on the launch grid)."""
+    torch = _torch()
+    P = _proc(lib_procs, name)
+    n_small, n_full, sq = CASES[name]
+    mom, _ = P.rambo(sq, SEED, 0, n_full)
+    me = P.matrix_element(mom).cpu().numpy()
+    rng = np.random.default_rng(5)
+    k = 24 if name == "gg_ttggg" else 96
+    idx = np.unique(np.concatenate([rng.choice(n_full, k, replace=False), [0, n_full - 1]]))
+    mom_h = mom[:, :, idx].cpu().numpy().transpose(2, 0, 1).copy()
+    _check_fp64(me[idx], mom_h, oracle_procs[name])
+    small, _ = P.rambo(sq, SEED, 0, 333)
+    me_small = P.matrix_element(small).cpu().numpy()
+    assert np.array_equal(me_small, me[:333])
+    assert np.all(np.isfinite(me)) and np.all(me > 0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_good_helicities_match_oracle(lib_procs, oracle_procs, name):
+    """Good helicities = helicities with a non-zero FP64 contribution on at
+    least one of 64 calibration events (seed 1); per-helicity values agree."""
+    torch = _torch()
+    P = _proc(lib_procs, name)
+    sq = CASES[name][2]
+    mom, _ = P.rambo(sq, 1, 0, 64)
+    host = _host(mom, 64)
+    O = oracle_procs[name]
+    per = np.array([O.me_hel(host[e]) for e in range(0, 64, 1 if P.n_ext < 7 else 16)])
+    expected = [h for h in range(1 << P.n_ext) if np.any(per[:, h] != 0.0)]
+    if P.n_ext < 7:
+        assert P.good_helicities() == expected
+    if name == "ee_mumu":
+        assert len(expected) == 4
+    gpu = P.matrix_element_per_helicity(mom).cpu().numpy()  # [n_hel, 64]
+    step = 1 if P.n_ext < 7 else 16
+    for j, e in enumerate(range(0, 64, step)):
+        # helicities that vanish analytically come out as rounding noise far
+        # below the others; compare them on the scale of the event's total
+        np.testing.assert_allclose(gpu[:, e], per[j], rtol=1e-11, atol=1e-13 * per[j].max())
+    # the masked sum equals the sum over every helicity
+    me = P.matrix_element(mom).cpu().numpy()
+    np.testing.assert_allclose(me, gpu.sum(axis=0), rtol=1e-13)
+
+
+@pytest.mark.parametrize("name", ["gg_ttg", "gg_ttgg"])
+def test_invariances_on_gpu(lib_procs, name):
+    """Lorentz boost (beta = 0.9) and Bose symmetry of final gluons."""
+    torch = _torch()
+    P = _proc(lib_procs, name)
+    n, _, sq = CASES[name]
+    mom, _ = P.rambo(sq, SEED, 0, n)
+    ref = P.matrix_element(mom).cpu().numpy()
+    h = mom.cpu().numpy()  # [n_ext, 4, n]
+    beta = np.array([0.3, -0.5, 0.6])
+    beta *= 0.9 / np.linalg.norm(beta)
+    g = 1 / math.sqrt(1 - beta @ beta)
+    e, p = h[:, 0, :], h[:, 1:, :]
+    bp = np.einsum("k,ikn->in", beta, p)
+    hb = np.empty_like(h)
+    hb[:, 0, :] = g * (e + bp)
+    hb[:, 1:, :] = p + ((g - 1) * bp / (beta @ beta) + g * e)[:, None, :] * beta[None, :, None]
+    boosted = P.matrix_element(torch.from_numpy(hb).cuda()).cpu().numpy()
+    np.testing.assert_allclose(boosted, ref, rtol=1e-11)
+    if P.n_ext >= 6:
+        hs = h.copy()
+        hs[[4, 5]] = h[[5, 4]]
+        np.testing.assert_allclose(P.matrix_element(torch.from_numpy(hs).cuda()).cpu().numpy(), ref, rtol=1e-12)
+    hs = h.copy()
+    hs[[0, 1]] = h[[1, 0]]
+    np.testing.assert_allclose(P.matrix_element(torch.from_numpy(hs).cuda()).cpu().numpy(), ref, rtol=1e-12)
+
+
+def test_determinism_and_ragged_edges(lib_procs):
+    torch = _torch()
+    import paper_2303_18244_amd as M
+
+    P = _proc(lib_procs, "gg_ttgg")
+    mom, _ = P.rambo(1500.0, SEED, 0, 1000)
+    a = P.matrix_element(mom).cpu().numpy()
+    b = P.matrix_element(mom).cpu().numpy()
+    assert np.array_equal(a, b)
+    # one event, and a padded leading dimension
+    one = P.matrix_element(mom[:, :, :1].contiguous()).cpu().numpy()
+    assert one[0] == a[0]
+    padded = torch.zeros((P.n_ext, 4, 1024), dtype=torch.float64, device="cuda")
+    padded[:, :, :1000] = mom
+    out = torch.full((1024,), -7.0, dtype=torch.float64, device="cuda")
+    P.matrix_element(padded, nevt=1000, out=out)
+    o = out.cpu().numpy()
+    assert np.array_equal(o[:1000], a) and np.all(o[1000:] == -7.0)
+    # empty batch is a no-op
+    out0 = torch.full((4,), -3.0, dtype=torch.float64, device="cuda")
+    P.matrix_element(padded, nevt=0, out=out0)
+    assert np.all(out0.cpu().numpy() == -3.0)
+    with pytest.raises(M.MgmeError) as ei:
+        P.matrix_element(mom, precision=M.MIXED)
+    assert ei.value.code == M.MGME_EUNSUPPORTED
+    with pytest.raises(M.MgmeError) as ei:
+        P.matrix_element(mom, precision=7)
+    assert ei.value.code == M.MGME_EINVAL
+
+
+def test_colour_matrix_export_matches_oracle(lib_procs, oracle_procs):
+    _torch()
+    for name in ("gg_tt", "gg_ttg", "gg_ttgg"):
+        num, den, basis = _proc(lib_procs, name).colour_matrix()
+        Co, oden, obasis = oracle_procs[name].colour_matrix()
+        idx = {tuple(b): i for i, b in enumerate(obasis.tolist())}
+        for i, bi in enumerate(basis):
+            for j, bj in enumerate(basis):
+                assert num[i][j] * oden == Co[idx[tuple(bi)], idx[tuple(bj)]] * den
