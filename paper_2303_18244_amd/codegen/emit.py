@@ -78,56 +78,50 @@ def colour_sum_lines(C: List[List[Fraction]], den: int) -> List[str]:
     return out
 
 
-def emit_gg_process(name: str, pdg: List[int]) -> Dict:
-    """g g -> t t~ + n g."""
-    n_ext = len(pdg)
-    incoming = [i < 2 for i in range(n_ext)]
-    gluon_legs = [i for i, x in enumerate(pdg) if x == 21]
-    q_leg, qb_leg = pdg.index(6), pdg.index(-6)
-    terms, n_diag = enumerate_terms(gluon_legs)
-    flows = col.basis(gluon_legs)
-    C = col.colour_matrix(flows)
-    cden = 1
-    for row in C:
-        for v in row:
-            cden = lcm(cden, v.denominator)
-    sched = Schedule(terms, q_leg, qb_leg, flows)
-    em = Emitter(n_ext, incoming, [abs(x) == 6 for x in pdg])
+class GGBody:
+    """Straight-line evaluation of a list of amplitude vertices of one
+    helicity configuration: external wavefunctions, the currents each
+    amplitude needs (computed at first use), and the amplitude values."""
 
-    # external wavefunctions
-    names: Dict[tuple, str] = {}
-    fresh_fn: Dict[str, str] = {}
-    for i in range(n_ext):
-        lam = f"((hc >> {n_ext - 1 - i}) & 1 ? 1 : -1)"
-        if pdg[i] == 21:
-            em.w(f"const wf<T> x{i} = ext_vec<T>(q[{i}], {lam}, {'false' if incoming[i] else 'true'});")
-            fresh_fn[f"x{i}"] = "fresh_pol"
-        elif i == q_leg:
-            em.w(f"const wf<T> x{i} = ext_bra<T>(q[{i}], mt, {lam}, false);")
-        else:
-            em.w(f"const wf<T> x{i} = ext_ket<T>(q[{i}], mt, {lam}, true);")
-        names[("X", i)] = f"x{i}"
-    inmask = sum(1 << i for i in range(n_ext) if incoming[i])
+    def __init__(self, sched: Schedule, pdg: List[int], em: Emitter):
+        self.sched = sched
+        self.em = em
+        n_ext = len(pdg)
+        incoming = [i < 2 for i in range(n_ext)]
+        q_leg = pdg.index(6)
+        self.names: Dict[tuple, str] = {}
+        self.fresh_fn: Dict[str, str] = {}
+        for i in range(n_ext):
+            lam = f"((hc >> {n_ext - 1 - i}) & 1 ? 1 : -1)"
+            if pdg[i] == 21:
+                em.w(f"const wf<T> x{i} = ext_vec<T>(q[{i}], {lam}, {'false' if incoming[i] else 'true'});")
+                self.fresh_fn[f"x{i}"] = "fresh_pol"
+            elif i == q_leg:
+                em.w(f"const wf<T> x{i} = ext_bra<T>(q[{i}], mt, {lam}, false);")
+            else:
+                em.w(f"const wf<T> x{i} = ext_ket<T>(q[{i}], mt, {lam}, true);")
+            self.names[("X", i)] = f"x{i}"
+        self.inmask = sum(1 << i for i in range(n_ext) if incoming[i])
+        self.counter = 0
 
-    def fr(v: str) -> str:
-        return f"{fresh_fn.get(v, 'fresh')}({v})"
+    def fr(self, v: str) -> str:
+        return f"{self.fresh_fn.get(v, 'fresh')}({v})"
 
-    def mom(var: str, mask: int) -> str:
-        return (f"double {var}d[4]; flow_momentum<{mask}u, {inmask}u, NEXT>({var}d, q); "
+    def mom(self, var: str, mask: int) -> str:
+        return (f"double {var}d[4]; flow_momentum<{mask}u, {self.inmask}u, NEXT>({var}d, q); "
                 f"T {var}[4]; to_t({var}, {var}d);")
 
-    def leg_mask(k) -> int:
-        return sched.currents[k].mask if k[0] != "X" else 1 << k[1]
+    def leg_mask(self, k) -> int:
+        return self.sched.currents[k].mask if k[0] != "X" else 1 << k[1]
 
-    counter = [0]
-
-    def need(key) -> str:
-        if key in names:
-            return names[key]
-        cur = sched.currents[key]
-        ins = [need(k) for k in cur.inputs]
-        v = f"w{counter[0]}"
-        counter[0] += 1
+    def need(self, key) -> str:
+        if key in self.names:
+            return self.names[key]
+        em, fr, mom = self.em, self.fr, self.mom
+        cur = self.sched.currents[key]
+        ins = [self.need(k) for k in cur.inputs]
+        v = f"w{self.counter}"
+        self.counter += 1
         em.w(f"wf<T> {v};")
         if cur.routine == "vvv_vec":
             c1, c2 = cur.tree.children
@@ -135,51 +129,141 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
             em.w("  const double Pd[4] = {k1d[0] + k2d[0], k1d[1] + k2d[1], k1d[2] + k2d[2], k1d[3] + k2d[3]};")
             em.w(f"  {v} = vvv_vec<T>({fr(ins[0])}, k1, {fr(ins[1])}, k2, (T)inv_virt(Pd, 0.0)); }}")
         elif cur.routine == "vvvv_vec":
-            em.w(f"{{ double Pd[4]; flow_momentum<{cur.mask}u, {inmask}u, NEXT>(Pd, q);")
+            em.w(f"{{ double Pd[4]; flow_momentum<{cur.mask}u, {self.inmask}u, NEXT>(Pd, q);")
             em.w(f"  {v} = vvvv_vec<T, {cur.tree.s}>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])}, "
                  f"(T)inv_virt(Pd, 0.0)); }}")
         elif cur.routine in ("ket_prop", "bra_prop"):
             em.w(f"{{ {mom('P', cur.mask)}")
             em.w(f"  {v} = {cur.routine}<T>({fr(ins[0])}, {fr(ins[1])}, P, (T)mt, (T)inv_virt(Pd, mt)); }}")
         elif cur.routine == "ffv_vec":
-            em.w(f"{{ double Pd[4]; flow_momentum<{cur.mask}u, {inmask}u, NEXT>(Pd, q);")
+            em.w(f"{{ double Pd[4]; flow_momentum<{cur.mask}u, {self.inmask}u, NEXT>(Pd, q);")
             em.w(f"  {v} = ffv_vec<T>({fr(ins[0])}, {fr(ins[1])}, (T)inv_virt(Pd, 0.0)); }}")
         else:
             raise ValueError(cur.routine)
-        names[key] = v
+        self.names[key] = v
         return v
 
-    amps = sched.low_pressure_order()
-    ncol = len(flows)
-    em.w(f"cx<T> J[{ncol}];")
-    em.w(f"for (int s = 0; s < {ncol}; ++s) J[s] = mk<T>((T)0, (T)0);")
-    for a in amps:
-        ins = [need(k) for k in a.inputs]
+    def amplitude(self, a) -> None:
+        """Opens a block defining `a`, the amplitude value; the caller closes it."""
+        em, fr = self.em, self.fr
+        ins = [self.need(k) for k in a.inputs]
         if a.routine == "ffv_amp":
             em.w(f"{{ const cx<T> a = ffv_amp<T>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])});")
         elif a.routine == "vvv_amp":
-            m1, m2, m3 = (leg_mask(k) for k in a.inputs)
-            em.w(f"{{ {mom('k1', m1)} {mom('k2', m2)} {mom('k3', m3)}")
+            m1, m2, m3 = (self.leg_mask(k) for k in a.inputs)
+            em.w(f"{{ {self.mom('k1', m1)} {self.mom('k2', m2)} {self.mom('k3', m3)}")
             em.w(f"  const cx<T> a = vvv_amp<T>({fr(ins[0])}, k1, {fr(ins[1])}, k2, {fr(ins[2])}, k3);")
         else:
             em.w(f"{{ const cx<T> a = vvvv_amp<T, {a.s}>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])}, "
                  f"{fr(ins[3])});")
+
+
+def _gg_setup(pdg: List[int]):
+    n_ext = len(pdg)
+    gluon_legs = [i for i, x in enumerate(pdg) if x == 21]
+    terms, n_diag = enumerate_terms(gluon_legs)
+    flows = col.basis(gluon_legs)
+    C = col.colour_matrix(flows)
+    cden = 1
+    for row in C:
+        for v in row:
+            cden = lcm(cden, v.denominator)
+    sched = Schedule(terms, pdg.index(6), pdg.index(-6), flows)
+    return n_ext, gluon_legs, terms, n_diag, flows, C, cden, sched
+
+
+def _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, body, **extra):
+    incoming = [i < 2 for i in range(n_ext)]
+    n_final_g = len([i for i in gluon_legs if not incoming[i]])
+    meta = dict(name=name, pdg=pdg, n_ext=n_ext, n_diagrams=n_diag, n_terms=len(terms), ncol=ncol,
+                cden=cden, n_currents=len(sched.currents), n_amps=len(sched.amps), gs_power=2 * len(gluon_legs),
+                spin_colour_avg=4 * 64, ident=_fact(n_final_g), kind="qcd",
+                flops_per_hel=flops_hel, flops_per_event=8 * 2 ** n_ext, body=body)
+    meta.update(extra)
+    return meta
+
+
+def emit_gg_process(name: str, pdg: List[int]) -> Dict:
+    """g g -> t t~ + n g, fused: the colour-flow amplitudes J stay in
+    registers and the colour sum runs in the same kernel."""
+    n_ext, gluon_legs, terms, n_diag, flows, C, cden, sched = _gg_setup(pdg)
+    em = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
+    body = GGBody(sched, pdg, em)
+    ncol = len(flows)
+    em.w(f"cx<T> J[{ncol}];")
+    em.w(f"for (int s = 0; s < {ncol}; ++s) J[s] = mk<T>((T)0, (T)0);")
+    for a in sched.low_pressure_order():
+        body.amplitude(a)
         upd = " ".join(f"acc(J[{f}], a, {re}, {im});" for f, re, im in a.coeffs)
         em.w(f"  {upd} }}")
     em.w("double me = 0.0;")
     for line in colour_sum_lines(C, cden):
         em.w(line)
-
-    body = "\n".join(em.lines)
-    k = len(gluon_legs)
-    n_final_g = len([i for i in gluon_legs if not incoming[i]])
     flops_hel = sched.flops_per_helicity() + 2 * ncol * ncol + 4 * ncol + 90 * n_ext
-    meta = dict(name=name, pdg=pdg, n_ext=n_ext, n_diagrams=n_diag, n_terms=len(terms), ncol=ncol,
-                cden=cden, n_currents=len(sched.currents), n_amps=len(amps), gs_power=2 * k,
-                spin_colour_avg=4 * 64, ident=_fact(n_final_g), kind="qcd",
-                flops_per_hel=flops_hel, flops_per_event=8 * 2 ** n_ext,
-                body=body)
-    return meta
+    return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "\n".join(em.lines))
+
+
+def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int) -> Dict:
+    """g g -> t t~ + n g, staged for processes whose colour-flow vector does
+    not fit in registers: the amplitude vertices, in low-register-pressure
+    order, are split into `n_chunks` kernels.  Each kernel keeps at most
+    `budget` flow accumulators in registers; an accumulator is stored to its
+    own slot of a device buffer when its flow gets no further contribution in
+    the chunk or when it is the open flow used furthest in the future.  A
+    colour kernel sums the slots of every flow and forms Re(J^dagger C J)."""
+    n_ext, gluon_legs, terms, n_diag, flows, C, cden, sched = _gg_setup(pdg)
+    ncol = len(flows)
+    order = sched.low_pressure_order()
+    n = len(order)
+    chunks = [order[i * n // n_chunks:(i + 1) * n // n_chunks] for i in range(n_chunks)]
+    slot_flow: List[int] = []
+    chunk_bodies = []
+    flops_hel = 0
+    for chunk in chunks:
+        em = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
+        body = GGBody(sched, pdg, em)
+        uses: Dict[int, List[int]] = {}
+        for j, a in enumerate(chunk):
+            for f, _, _ in a.coeffs:
+                uses.setdefault(f, []).append(j)
+        ptr = {f: 0 for f in uses}
+        open_acc: Dict[int, str] = {}
+        nacc = [0]
+
+        def flush(f):
+            v = open_acc.pop(f)
+            em.w(f"Jp[{len(slot_flow)}ll * ldp] = {v};")
+            slot_flow.append(f)
+
+        for j, a in enumerate(chunk):
+            body.amplitude(a)
+            parts = []
+            for f, re, im in a.coeffs:
+                ptr[f] += 1
+                if f in open_acc:
+                    parts.append(f"acc({open_acc[f]}, a, {re}, {im});")
+                else:
+                    v = f"j{nacc[0]}"
+                    nacc[0] += 1
+                    open_acc[f] = v
+                    em.lines.insert(len(em.lines) - (1 if a.routine != "vvv_amp" else 2), f"    cx<T> {v};")
+                    parts.append(f"{v} = mk<T>((T)0, (T)0); acc({v}, a, {re}, {im});")
+            em.w(f"  {' '.join(parts)} }}")
+            for f in [f for f in open_acc if ptr[f] >= len(uses[f])]:
+                flush(f)
+            while len(open_acc) > budget:
+                far = max(open_acc, key=lambda f: uses[f][ptr[f]])
+                flush(far)
+        for f in list(open_acc):
+            flush(f)
+        chunk_bodies.append("\n".join(em.lines))
+        flops_hel += sum(FLOPS[a.routine] + FLOPS["acc"] * len(a.coeffs) for a in chunk)
+        flops_hel += sum(sched.currents[k].cost for k in body.names if k[0] != "X")
+    flops_hel += 2 * ncol * ncol + 4 * ncol + 2 * len(slot_flow) + 90 * n_ext * n_chunks
+    slots_of = [[s for s, f in enumerate(slot_flow) if f == fl] for fl in range(ncol)]
+    return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "",
+                    staged=True, chunk_bodies=chunk_bodies, n_slots=len(slot_flow), slots_of=slots_of,
+                    colour_num=[int(v * cden) for row in C for v in row])
 
 
 def _fact(n: int) -> int:
@@ -284,3 +368,209 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
 
 def kernel_source(meta: Dict) -> str:
     return KERNEL_TEMPLATE.format(title=" ".join(str(x) for x in meta["pdg"]), **meta)
+
+
+CHUNK_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: diagram chunk {chunk} of {n_chunks}.
+// Each lane evaluates one (event, good helicity); its colour-flow partial sums
+// are stored to slots of a device buffer laid out [helicity][slot][event].
+#include "../helamp.h"
+#include "../me_kernel.h"
+
+namespace mgme {{
+namespace {name} {{
+namespace c{chunk} {{
+
+constexpr int NEXT = {n_ext};
+constexpr long long NSLOT = {n_slots};
+
+template <typename T>
+__global__ void __launch_bounds__(256) chunk_kernel(const double* __restrict__ mom, long long nevt, long long ld,
+                                                   const MeArgs args, cx<T>* __restrict__ Jpart, long long ldp) {{
+  // 64 consecutive events per wave, one helicity per wave (uniform)
+  const int hs = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (threadIdx.x >> 6));
+  const long long e = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
+  if (hs >= args.nhel || e >= nevt) return;
+  const int hc = args.hel[hs];
+  const double mt = args.mt;
+  double q[NEXT][4];
+#pragma unroll
+  for (int i = 0; i < NEXT; ++i)
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) q[i][mu] = mom[(long long)(i * 4 + mu) * ld + e];
+  cx<T>* __restrict__ Jp = Jpart + (long long)hs * NSLOT * ldp + e;
+{body}
+}}
+
+}}  // namespace c{chunk}
+}}  // namespace {name}
+}}  // namespace mgme
+
+extern "C" hipError_t mgme_{name}_chunk{chunk}(int prec, dim3 grid, const double* mom, long long nevt, long long ld,
+                                              const mgme::MeArgs* args, void* Jpart, long long ldp,
+                                              hipStream_t stream) {{
+  if (prec == 0)
+    mgme::{name}::c{chunk}::chunk_kernel<double><<<grid, 256, 0, stream>>>(mom, nevt, ld, *args,
+        (mgme::cx<double>*)Jpart, ldp);
+  else
+    mgme::{name}::c{chunk}::chunk_kernel<float><<<grid, 256, 0, stream>>>(mom, nevt, ld, *args,
+        (mgme::cx<float>*)Jpart, ldp);
+  return hipGetLastError();
+}}
+"""
+
+COLOUR_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: colour sum and driver.
+// {n_diagrams} Feynman diagrams ({n_terms} colour/Lorentz terms), {ncol} colour flows, evaluated by
+// {n_chunks} diagram kernels writing {n_slots} colour-flow partial sums per (event, helicity).
+#include "../helamp.h"
+#include "../me_kernel.h"
+
+namespace mgme {{
+namespace {name} {{
+
+constexpr int NCOL = {ncol};
+constexpr long long NSLOT = {n_slots};
+constexpr int NB = {nb};  // flows per block of the quadratic form
+
+// colour-matrix numerators (common denominator applied in the final factor)
+__constant__ double kC[NCOL * NCOL] = {{{cnum}}};
+// slots holding the partial sums of each flow
+__constant__ short kSlotStart[NCOL + 1] = {{{slot_start}}};
+__constant__ short kSlots[NSLOT] = {{{slot_list}}};
+
+// Sums the slots of every flow into Jc (double, [helicity][flow][event]), then
+// me_h = sum_st C_st Re(conj(J_s) J_t), with blocks of NB flows of C J held in
+// registers while J streams from memory.
+template <typename T>
+__global__ void __launch_bounds__(256) colour_kernel(long long nevt, const MeArgs args,
+                                                    const cx<T>* __restrict__ Jpart, long long ldp,
+                                                    cx<double>* __restrict__ Jc, double* __restrict__ out,
+                                                    long long ldo, double scale) {{
+  const int hs = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (threadIdx.x >> 6));
+  const long long e = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
+  if (hs >= args.nhel || e >= nevt) return;
+  const cx<T>* __restrict__ Jp = Jpart + (long long)hs * NSLOT * ldp + e;
+  cx<double>* __restrict__ J = Jc + (long long)hs * NCOL * ldp + e;
+  for (int s = 0; s < NCOL; ++s) {{
+    double re = 0.0, im = 0.0;
+    for (int k = kSlotStart[s]; k < kSlotStart[s + 1]; ++k) {{
+      const cx<T> v = Jp[(long long)kSlots[k] * ldp];
+      re += (double)v.re;
+      im += (double)v.im;
+    }}
+    J[(long long)s * ldp] = cx<double>{{re, im}};
+  }}
+  double me = 0.0;
+  for (int b = 0; b < NCOL; b += NB) {{
+    double yr[NB], yi[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) yr[k] = yi[k] = 0.0;
+    for (int t = 0; t < NCOL; ++t) {{
+      const cx<double> jt = J[(long long)t * ldp];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {{
+        const double c = kC[(b + k) * NCOL + t];
+        yr[k] += c * jt.re;
+        yi[k] += c * jt.im;
+      }}
+    }}
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {{
+      const cx<double> js = J[(long long)(b + k) * ldp];
+      me += js.re * yr[k] + js.im * yi[k];
+    }}
+  }}
+  out[(long long)hs * ldo + e] = me * scale;
+}}
+
+// out[e] = factor * sum over helicities of me_h[e], in helicity order.
+__global__ void __launch_bounds__(256) helicity_sum_kernel(long long nevt, int nhel, const double* __restrict__ meh,
+                                                          long long ldh, double factor, double* __restrict__ out) {{
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nevt) return;
+  double s = 0.0;
+  for (int h = 0; h < nhel; ++h) s += meh[(long long)h * ldh + e];
+  out[e] = s * factor;
+}}
+
+}}  // namespace {name}
+}}  // namespace mgme
+
+{chunk_decls}
+
+// Events are processed in sub-batches whose staging buffers fit the
+// workspace bound; the workspace comes from the stream-ordered allocator.
+extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mom, long long nevt, long long ld,
+                                          const mgme::MeArgs* args, double* out, long long ldo,
+                                          hipStream_t stream) {{
+  using namespace mgme::{name};
+  const int nh = args->nhel;
+  const size_t tsize = prec == 0 ? sizeof(mgme::cx<double>) : sizeof(mgme::cx<float>);
+  const size_t per_event = (size_t)nh * (NSLOT * tsize + NCOL * sizeof(mgme::cx<double>) + sizeof(double));
+  const size_t budget = (size_t){workspace_bytes};
+  long long sub = (long long)(budget / per_event) / 64 * 64;
+  if (sub < 64) sub = 64;
+  if (sub > nevt) sub = (nevt + 63) / 64 * 64;
+  const size_t bytes = per_event * (size_t)sub;
+  char* ws = nullptr;
+  hipError_t err = hipMallocAsync((void**)&ws, bytes, stream);
+  if (err != hipSuccess) return err;
+  void* Jpart = ws;
+  mgme::cx<double>* Jc = (mgme::cx<double>*)(ws + (size_t)nh * NSLOT * tsize * sub);
+  double* meh = (double*)((char*)Jc + (size_t)nh * NCOL * sizeof(mgme::cx<double>) * sub);
+  const double factor = args->factor;
+  for (long long start = 0; start < nevt && err == hipSuccess; start += sub) {{
+    const long long n = (nevt - start < sub) ? nevt - start : sub;
+    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((nh + 3) / 4));
+{chunk_calls}
+    if (err != hipSuccess) break;
+    if (per_hel) {{
+      if (prec == 0)
+        colour_kernel<double><<<grid, 256, 0, stream>>>(n, *args, (const mgme::cx<double>*)Jpart, sub, Jc,
+                                                       out + start, ldo, factor);
+      else
+        colour_kernel<float><<<grid, 256, 0, stream>>>(n, *args, (const mgme::cx<float>*)Jpart, sub, Jc,
+                                                      out + start, ldo, factor);
+    }} else {{
+      if (prec == 0)
+        colour_kernel<double><<<grid, 256, 0, stream>>>(n, *args, (const mgme::cx<double>*)Jpart, sub, Jc, meh,
+                                                       sub, 1.0);
+      else
+        colour_kernel<float><<<grid, 256, 0, stream>>>(n, *args, (const mgme::cx<float>*)Jpart, sub, Jc, meh,
+                                                      sub, 1.0);
+      helicity_sum_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(n, nh, meh, sub, factor, out + start);
+    }}
+    err = hipGetLastError();
+  }}
+  const hipError_t ferr = hipFreeAsync(ws, stream);
+  return err != hipSuccess ? err : ferr;
+}}
+"""
+
+
+def staged_sources(meta: Dict, workspace_bytes: int = 6 << 30, nb: int = 40) -> Dict[str, str]:
+    """File name -> source for a staged process."""
+    title = " ".join(str(x) for x in meta["pdg"])
+    out = {}
+    nchunk = len(meta["chunk_bodies"])
+    for c, body in enumerate(meta["chunk_bodies"]):
+        out[f"me_{meta['name']}_chunk{c}.hip"] = CHUNK_TEMPLATE.format(
+            title=title, chunk=c, n_chunks=nchunk, name=meta["name"], n_ext=meta["n_ext"],
+            n_slots=meta["n_slots"], body=body)
+    slot_start, slot_list = [0], []
+    for s in meta["slots_of"]:
+        slot_list += s
+        slot_start.append(len(slot_list))
+    decls = "\n".join(
+        f'extern "C" hipError_t mgme_{meta["name"]}_chunk{c}(int, dim3, const double*, long long, long long, '
+        f'const mgme::MeArgs*, void*, long long, hipStream_t);' for c in range(nchunk))
+    calls = "\n".join(
+        f"    if (err == hipSuccess) err = mgme_{meta['name']}_chunk{c}(prec, grid, mom + start, n, ld, args, "
+        f"Jpart, sub, stream);" for c in range(nchunk))
+    assert meta["ncol"] % nb == 0
+    out[f"me_{meta['name']}.hip"] = COLOUR_TEMPLATE.format(
+        title=title, name=meta["name"], n_diagrams=meta["n_diagrams"], n_terms=meta["n_terms"],
+        ncol=meta["ncol"], n_chunks=nchunk, n_slots=meta["n_slots"], nb=nb,
+        cnum=", ".join(f"{v}.0" for v in meta["colour_num"]),
+        slot_start=", ".join(map(str, slot_start)), slot_list=", ".join(map(str, slot_list)),
+        chunk_decls=decls, chunk_calls=calls, workspace_bytes=workspace_bytes)
+    return out
