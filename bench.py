@@ -68,6 +68,9 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="gg_ttgg", choices=list(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="instead of the benchmark, time a plain device-to-device copy of this many bytes "
+                         "(the reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported (events are independent, "
@@ -76,6 +79,20 @@ def main(argv=None) -> int:
 
     import numpy as np
     import torch
+
+    if a.copy_bytes:
+        n = a.copy_bytes // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        print(json.dumps({"copy_bytes": n * 8, "ms_per_copy": dt * 1e3, "GB_per_s": 2 * n * 8 / dt * 1e-9}))
+        return 0
 
     import paper_2303_18244_amd as M
 

@@ -95,17 +95,18 @@ class GGBody:
             lam = f"((hc >> {n_ext - 1 - i}) & 1 ? 1 : -1)"
             if pdg[i] == 21:
                 em.w(f"const wf<T> x{i} = ext_vec<T>(q[{i}], {lam}, {'false' if incoming[i] else 'true'});")
-                self.fresh_fn[f"x{i}"] = "fresh_pol"
             elif i == q_leg:
                 em.w(f"const wf<T> x{i} = ext_bra<T>(q[{i}], mt, {lam}, false);")
             else:
                 em.w(f"const wf<T> x{i} = ext_ket<T>(q[{i}], mt, {lam}, true);")
             self.names[("X", i)] = f"x{i}"
+            self.fresh_fn[f"x{i}"] = ""
         self.inmask = sum(1 << i for i in range(n_ext) if incoming[i])
         self.counter = 0
 
     def fr(self, v: str) -> str:
-        return f"{self.fresh_fn.get(v, 'fresh')}({v})"
+        fn = self.fresh_fn.get(v, "fresh")
+        return f"{fn}({v})" if fn else v
 
     def mom(self, var: str, mask: int) -> str:
         return (f"double {var}d[4]; flow_momentum<{mask}u, {self.inmask}u, NEXT>({var}d, q); "
@@ -203,22 +204,30 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
     return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "\n".join(em.lines))
 
 
-def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int) -> Dict:
+def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefetch: int = 6) -> Dict:
     """g g -> t t~ + n g, staged for processes whose colour-flow vector does
-    not fit in registers: the amplitude vertices, in low-register-pressure
+    not fit in registers.  The amplitude vertices, in low-register-pressure
     order, are split into `n_chunks` kernels.  Each kernel keeps at most
-    `budget` flow accumulators in registers; an accumulator is stored to its
-    own slot of a device buffer when its flow gets no further contribution in
-    the chunk or when it is the open flow used furthest in the future.  A
-    colour kernel sums the slots of every flow and forms Re(J^dagger C J)."""
+    `budget` flow accumulators in registers and folds an accumulator into the
+    flow vector J in device memory when its flow gets no further contribution
+    in the chunk, or when it is the open flow used furthest in the future:
+      - the first write of a flow (in kernel order) is a plain store;
+      - a flow written by an earlier kernel is read, added and stored, the
+        read issued `prefetch` folds ahead so that it is in flight while the
+        kernel keeps computing;
+      - a flow already folded in the same kernel goes to an overflow slot
+        (a kernel never reads back its own stores).
+    A colour kernel adds the overflow slots and forms Re(J^dagger C J)."""
     n_ext, gluon_legs, terms, n_diag, flows, C, cden, sched = _gg_setup(pdg)
     ncol = len(flows)
     order = sched.low_pressure_order()
     n = len(order)
     chunks = [order[i * n // n_chunks:(i + 1) * n // n_chunks] for i in range(n_chunks)]
-    slot_flow: List[int] = []
+    written: set = set()
+    overflow_flow: List[int] = []
     chunk_bodies = []
     flops_hel = 0
+    n_rmw = 0
     for chunk in chunks:
         em = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
         body = GGBody(sched, pdg, em)
@@ -228,12 +237,27 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int) -> Dic
                 uses.setdefault(f, []).append(j)
         ptr = {f: 0 for f in uses}
         open_acc: Dict[int, str] = {}
+        folded_here: set = set()
+        fold_lines: List[int] = []          # line index of every fold in this chunk
+        rmw: List[tuple] = []               # (fold number, flow, prefetch variable)
         nacc = [0]
 
-        def flush(f):
+        def fold(f):
             v = open_acc.pop(f)
-            em.w(f"Jp[{len(slot_flow)}ll * ldp] = {v};")
-            slot_flow.append(f)
+            nonlocal n_rmw
+            if f in folded_here:
+                em.w(f"Ov[{len(overflow_flow)}ll * ldp] = {v};")
+                overflow_flow.append(f)
+            elif f not in written:
+                em.w(f"Jc[{f}ll * ldp] = {v};")
+                written.add(f)
+            else:
+                pf = f"pf{len(rmw)}"
+                rmw.append((len(fold_lines), f, pf))
+                em.w(f"Jc[{f}ll * ldp] = {pf} + {v};")
+                n_rmw += 1
+            folded_here.add(f)
+            fold_lines.append(len(em.lines) - 1)
 
         for j, a in enumerate(chunk):
             body.amplitude(a)
@@ -250,20 +274,28 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int) -> Dic
                     parts.append(f"{v} = mk<T>((T)0, (T)0); acc({v}, a, {re}, {im});")
             em.w(f"  {' '.join(parts)} }}")
             for f in [f for f in open_acc if ptr[f] >= len(uses[f])]:
-                flush(f)
+                fold(f)
             while len(open_acc) > budget:
                 far = max(open_acc, key=lambda f: uses[f][ptr[f]])
-                flush(far)
+                fold(far)
         for f in list(open_acc):
-            flush(f)
+            fold(f)
+        # prefetch reads of J written by earlier kernels, `prefetch` folds ahead
+        inserts = []
+        for k, f, pf in rmw:
+            at = fold_lines[k - prefetch] + 1 if k >= prefetch else 0
+            inserts.append((at, f"    const cx<T> {pf} = Jc[{f}ll * ldp];"))
+        for at, line in sorted(inserts, key=lambda t: -t[0]):
+            em.lines.insert(at, line)
         chunk_bodies.append("\n".join(em.lines))
         flops_hel += sum(FLOPS[a.routine] + FLOPS["acc"] * len(a.coeffs) for a in chunk)
         flops_hel += sum(sched.currents[k].cost for k in body.names if k[0] != "X")
-    flops_hel += 2 * ncol * ncol + 4 * ncol + 2 * len(slot_flow) + 90 * n_ext * n_chunks
-    slots_of = [[s for s, f in enumerate(slot_flow) if f == fl] for fl in range(ncol)]
+    assert written == set(range(ncol)), "every flow receives a contribution"
+    flops_hel += 2 * ncol * ncol + 4 * ncol + 2 * (n_rmw + len(overflow_flow)) + 90 * n_ext * n_chunks
+    overflow_of = [[s for s, f in enumerate(overflow_flow) if f == fl] for fl in range(ncol)]
     return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "",
-                    staged=True, chunk_bodies=chunk_bodies, n_slots=len(slot_flow), slots_of=slots_of,
-                    colour_num=[int(v * cden) for row in C for v in row])
+                    staged=True, chunk_bodies=chunk_bodies, n_overflow=len(overflow_flow), n_rmw=n_rmw,
+                    overflow_of=overflow_of, colour_num=[int(v * cden) for row in C for v in row])
 
 
 def _fact(n: int) -> int:
@@ -381,11 +413,13 @@ namespace {name} {{
 namespace c{chunk} {{
 
 constexpr int NEXT = {n_ext};
-constexpr long long NSLOT = {n_slots};
+constexpr long long NCOL = {ncol};
+constexpr long long NOV = {n_overflow};
 
 template <typename T>
 __global__ void __launch_bounds__(256) chunk_kernel(const double* __restrict__ mom, long long nevt, long long ld,
-                                                   const MeArgs args, cx<T>* __restrict__ Jpart, long long ldp) {{
+                                                   const MeArgs args, cx<T>* __restrict__ Jbuf,
+                                                   cx<T>* __restrict__ Ovbuf, long long ldp) {{
   // 64 consecutive events per wave, one helicity per wave (uniform)
   const int hs = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (threadIdx.x >> 6));
   const long long e = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
@@ -397,7 +431,9 @@ __global__ void __launch_bounds__(256) chunk_kernel(const double* __restrict__ m
   for (int i = 0; i < NEXT; ++i)
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) q[i][mu] = mom[(long long)(i * 4 + mu) * ld + e];
-  cx<T>* __restrict__ Jp = Jpart + (long long)hs * NSLOT * ldp + e;
+  cx<T>* __restrict__ Jc = Jbuf + (long long)hs * NCOL * ldp + e;
+  cx<T>* __restrict__ Ov = Ovbuf + (long long)hs * NOV * ldp + e;
+  (void)Ov;
 {body}
 }}
 
@@ -406,21 +442,22 @@ __global__ void __launch_bounds__(256) chunk_kernel(const double* __restrict__ m
 }}  // namespace mgme
 
 extern "C" hipError_t mgme_{name}_chunk{chunk}(int prec, dim3 grid, const double* mom, long long nevt, long long ld,
-                                              const mgme::MeArgs* args, void* Jpart, long long ldp,
+                                              const mgme::MeArgs* args, void* Jbuf, void* Ovbuf, long long ldp,
                                               hipStream_t stream) {{
   if (prec == 0)
     mgme::{name}::c{chunk}::chunk_kernel<double><<<grid, 256, 0, stream>>>(mom, nevt, ld, *args,
-        (mgme::cx<double>*)Jpart, ldp);
+        (mgme::cx<double>*)Jbuf, (mgme::cx<double>*)Ovbuf, ldp);
   else
     mgme::{name}::c{chunk}::chunk_kernel<float><<<grid, 256, 0, stream>>>(mom, nevt, ld, *args,
-        (mgme::cx<float>*)Jpart, ldp);
+        (mgme::cx<float>*)Jbuf, (mgme::cx<float>*)Ovbuf, ldp);
   return hipGetLastError();
 }}
 """
 
 COLOUR_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: colour sum and driver.
 // {n_diagrams} Feynman diagrams ({n_terms} colour/Lorentz terms), {ncol} colour flows, evaluated by
-// {n_chunks} diagram kernels writing {n_slots} colour-flow partial sums per (event, helicity).
+// {n_chunks} diagram kernels that fold their partial colour-flow sums into J in device memory
+// ({n_rmw} read-modify-write folds and {n_overflow} overflow slots per (event, helicity)).
 #include "../helamp.h"
 #include "../me_kernel.h"
 
@@ -428,55 +465,45 @@ namespace mgme {{
 namespace {name} {{
 
 constexpr int NCOL = {ncol};
-constexpr long long NSLOT = {n_slots};
+constexpr long long NOV = {n_overflow};
 constexpr int NB = {nb};  // flows per block of the quadratic form
 
 // colour-matrix numerators (common denominator applied in the final factor)
 __constant__ double kC[NCOL * NCOL] = {{{cnum}}};
-// slots holding the partial sums of each flow
-__constant__ short kSlotStart[NCOL + 1] = {{{slot_start}}};
-__constant__ short kSlots[NSLOT] = {{{slot_list}}};
 
-// Sums the slots of every flow into Jc (double, [helicity][flow][event]), then
-// me_h = sum_st C_st Re(conj(J_s) J_t), with blocks of NB flows of C J held in
+// Adds the overflow slots to J (fixed at generation), then
+// me_h = sum_st C_st Re(conj(J_s) J_t) with blocks of NB flows of C J held in
 // registers while J streams from memory.
 template <typename T>
-__global__ void __launch_bounds__(256) colour_kernel(long long nevt, const MeArgs args,
-                                                    const cx<T>* __restrict__ Jpart, long long ldp,
-                                                    cx<double>* __restrict__ Jc, double* __restrict__ out,
-                                                    long long ldo, double scale) {{
+__global__ void __launch_bounds__(256) colour_kernel(long long nevt, const MeArgs args, cx<T>* __restrict__ Jbuf,
+                                                    const cx<T>* __restrict__ Ovbuf, long long ldp,
+                                                    double* __restrict__ out, long long ldo, double scale) {{
   const int hs = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (threadIdx.x >> 6));
   const long long e = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
   if (hs >= args.nhel || e >= nevt) return;
-  const cx<T>* __restrict__ Jp = Jpart + (long long)hs * NSLOT * ldp + e;
-  cx<double>* __restrict__ J = Jc + (long long)hs * NCOL * ldp + e;
-  for (int s = 0; s < NCOL; ++s) {{
-    double re = 0.0, im = 0.0;
-    for (int k = kSlotStart[s]; k < kSlotStart[s + 1]; ++k) {{
-      const cx<T> v = Jp[(long long)kSlots[k] * ldp];
-      re += (double)v.re;
-      im += (double)v.im;
-    }}
-    J[(long long)s * ldp] = cx<double>{{re, im}};
-  }}
+  cx<T>* __restrict__ J = Jbuf + (long long)hs * NCOL * ldp + e;
+  const cx<T>* __restrict__ Ov = Ovbuf + (long long)hs * NOV * ldp + e;
+  (void)Ov;
+{overflow_sums}
   double me = 0.0;
   for (int b = 0; b < NCOL; b += NB) {{
     double yr[NB], yi[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) yr[k] = yi[k] = 0.0;
     for (int t = 0; t < NCOL; ++t) {{
-      const cx<double> jt = J[(long long)t * ldp];
+      const cx<T> jt = J[(long long)t * ldp];
+      const double jr = (double)jt.re, ji = (double)jt.im;
 #pragma unroll
       for (int k = 0; k < NB; ++k) {{
         const double c = kC[(b + k) * NCOL + t];
-        yr[k] += c * jt.re;
-        yi[k] += c * jt.im;
+        yr[k] += c * jr;
+        yi[k] += c * ji;
       }}
     }}
 #pragma unroll
     for (int k = 0; k < NB; ++k) {{
-      const cx<double> js = J[(long long)(b + k) * ldp];
-      me += js.re * yr[k] + js.im * yi[k];
+      const cx<T> js = J[(long long)(b + k) * ldp];
+      me += (double)js.re * yr[k] + (double)js.im * yi[k];
     }}
   }}
   out[(long long)hs * ldo + e] = me * scale;
@@ -497,48 +524,44 @@ __global__ void __launch_bounds__(256) helicity_sum_kernel(long long nevt, int n
 
 {chunk_decls}
 
-// Events are processed in sub-batches whose staging buffers fit the
-// workspace bound; the workspace comes from the stream-ordered allocator.
+// Events are processed in sub-batches whose buffers fit the workspace bound;
+// the workspace comes from the stream-ordered allocator.
 extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                           const mgme::MeArgs* args, double* out, long long ldo,
                                           hipStream_t stream) {{
   using namespace mgme::{name};
   const int nh = args->nhel;
   const size_t tsize = prec == 0 ? sizeof(mgme::cx<double>) : sizeof(mgme::cx<float>);
-  const size_t per_event = (size_t)nh * (NSLOT * tsize + NCOL * sizeof(mgme::cx<double>) + sizeof(double));
+  const size_t per_event = (size_t)nh * ((NCOL + NOV) * tsize + sizeof(double));
   const size_t budget = (size_t){workspace_bytes};
   long long sub = (long long)(budget / per_event) / 64 * 64;
   if (sub < 64) sub = 64;
+  if (sub > {max_sub}) sub = {max_sub};
   if (sub > nevt) sub = (nevt + 63) / 64 * 64;
   const size_t bytes = per_event * (size_t)sub;
   char* ws = nullptr;
   hipError_t err = hipMallocAsync((void**)&ws, bytes, stream);
   if (err != hipSuccess) return err;
-  void* Jpart = ws;
-  mgme::cx<double>* Jc = (mgme::cx<double>*)(ws + (size_t)nh * NSLOT * tsize * sub);
-  double* meh = (double*)((char*)Jc + (size_t)nh * NCOL * sizeof(mgme::cx<double>) * sub);
+  void* Jbuf = ws;
+  void* Ovbuf = ws + (size_t)nh * NCOL * tsize * sub;
+  double* meh = (double*)(ws + (size_t)nh * (NCOL + NOV) * tsize * sub);
   const double factor = args->factor;
   for (long long start = 0; start < nevt && err == hipSuccess; start += sub) {{
     const long long n = (nevt - start < sub) ? nevt - start : sub;
     const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((nh + 3) / 4));
 {chunk_calls}
     if (err != hipSuccess) break;
-    if (per_hel) {{
-      if (prec == 0)
-        colour_kernel<double><<<grid, 256, 0, stream>>>(n, *args, (const mgme::cx<double>*)Jpart, sub, Jc,
-                                                       out + start, ldo, factor);
-      else
-        colour_kernel<float><<<grid, 256, 0, stream>>>(n, *args, (const mgme::cx<float>*)Jpart, sub, Jc,
-                                                      out + start, ldo, factor);
-    }} else {{
-      if (prec == 0)
-        colour_kernel<double><<<grid, 256, 0, stream>>>(n, *args, (const mgme::cx<double>*)Jpart, sub, Jc, meh,
-                                                       sub, 1.0);
-      else
-        colour_kernel<float><<<grid, 256, 0, stream>>>(n, *args, (const mgme::cx<float>*)Jpart, sub, Jc, meh,
-                                                      sub, 1.0);
+    double* dst = per_hel ? out + start : meh;
+    const long long ldd = per_hel ? ldo : sub;
+    const double sc = per_hel ? factor : 1.0;
+    if (prec == 0)
+      colour_kernel<double><<<grid, 256, 0, stream>>>(n, *args, (mgme::cx<double>*)Jbuf,
+                                                     (const mgme::cx<double>*)Ovbuf, sub, dst, ldd, sc);
+    else
+      colour_kernel<float><<<grid, 256, 0, stream>>>(n, *args, (mgme::cx<float>*)Jbuf,
+                                                    (const mgme::cx<float>*)Ovbuf, sub, dst, ldd, sc);
+    if (!per_hel)
       helicity_sum_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(n, nh, meh, sub, factor, out + start);
-    }}
     err = hipGetLastError();
   }}
   const hipError_t ferr = hipFreeAsync(ws, stream);
@@ -547,7 +570,7 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
 """
 
 
-def staged_sources(meta: Dict, workspace_bytes: int = 6 << 30, nb: int = 40) -> Dict[str, str]:
+def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 16384, nb: int = 30) -> Dict[str, str]:
     """File name -> source for a staged process."""
     title = " ".join(str(x) for x in meta["pdg"])
     out = {}
@@ -555,22 +578,25 @@ def staged_sources(meta: Dict, workspace_bytes: int = 6 << 30, nb: int = 40) -> 
     for c, body in enumerate(meta["chunk_bodies"]):
         out[f"me_{meta['name']}_chunk{c}.hip"] = CHUNK_TEMPLATE.format(
             title=title, chunk=c, n_chunks=nchunk, name=meta["name"], n_ext=meta["n_ext"],
-            n_slots=meta["n_slots"], body=body)
-    slot_start, slot_list = [0], []
-    for s in meta["slots_of"]:
-        slot_list += s
-        slot_start.append(len(slot_list))
+            ncol=meta["ncol"], n_overflow=max(1, meta["n_overflow"]), body=body)
+    sums = []
+    for fl, sl in enumerate(meta["overflow_of"]):
+        if not sl:
+            continue
+        terms_re = " + ".join(f"Ov[{k}ll * ldp].re" for k in sl)
+        terms_im = " + ".join(f"Ov[{k}ll * ldp].im" for k in sl)
+        sums.append(f"  {{ cx<T> v = J[{fl}ll * ldp]; v.re += {terms_re}; v.im += {terms_im}; "
+                    f"J[{fl}ll * ldp] = v; }}")
     decls = "\n".join(
         f'extern "C" hipError_t mgme_{meta["name"]}_chunk{c}(int, dim3, const double*, long long, long long, '
-        f'const mgme::MeArgs*, void*, long long, hipStream_t);' for c in range(nchunk))
+        f'const mgme::MeArgs*, void*, void*, long long, hipStream_t);' for c in range(nchunk))
     calls = "\n".join(
         f"    if (err == hipSuccess) err = mgme_{meta['name']}_chunk{c}(prec, grid, mom + start, n, ld, args, "
-        f"Jpart, sub, stream);" for c in range(nchunk))
+        f"Jbuf, Ovbuf, sub, stream);" for c in range(nchunk))
     assert meta["ncol"] % nb == 0
     out[f"me_{meta['name']}.hip"] = COLOUR_TEMPLATE.format(
         title=title, name=meta["name"], n_diagrams=meta["n_diagrams"], n_terms=meta["n_terms"],
-        ncol=meta["ncol"], n_chunks=nchunk, n_slots=meta["n_slots"], nb=nb,
-        cnum=", ".join(f"{v}.0" for v in meta["colour_num"]),
-        slot_start=", ".join(map(str, slot_start)), slot_list=", ".join(map(str, slot_list)),
-        chunk_decls=decls, chunk_calls=calls, workspace_bytes=workspace_bytes)
+        ncol=meta["ncol"], n_chunks=nchunk, n_overflow=max(1, meta["n_overflow"]), n_rmw=meta["n_rmw"], nb=nb,
+        cnum=", ".join(f"{v}.0" for v in meta["colour_num"]), overflow_sums="\n".join(sums),
+        chunk_decls=decls, chunk_calls=calls, workspace_bytes=workspace_bytes, max_sub=max_sub)
     return out
