@@ -66,7 +66,7 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="gg_ttgg", choices=list(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the benchmark, time a plain device-to-device copy of this many bytes "
@@ -97,7 +97,7 @@ def main(argv=None) -> int:
     import paper_2303_18244_amd as M
 
     key, nevt, sqrt_s = WORKLOADS[a.workload]
-    prec = M.FP64 if a.precision == "fp64" else M.FP32
+    prec = {"fp64": M.FP64, "fp32": M.FP32, "mixed": M.MIXED}[a.precision]
     P = M.Process(M.PROCESSES[key])
     info = P.info
     dev = torch.device("cuda", 0)
@@ -143,7 +143,7 @@ def main(argv=None) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": (value / PAPER_MES[(key, prec)]) if (key, prec) in PAPER_MES else None,
-        "dtype": "f64" if prec == M.FP64 else "f32",
+        "dtype": {M.FP64: "f64", M.FP32: "f32", M.MIXED: "f32+f16"}[prec],
         "data": "synthetic (RAMBO flat phase space, Philox seed 230318244)",
         "config": {"workload": key, "events_per_batch": nevt, "sqrt_s_gev": sqrt_s,
                    "precision": a.precision, "good_helicities": ngood, "diagrams": info["n_diagrams"],
@@ -151,7 +151,7 @@ def main(argv=None) -> int:
         "me_only": {"ms_per_launch": me_ms, "mes_per_s": nevt / (me_ms * 1e-3)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": f"me_kernel<{'double' if prec == M.FP64 else 'float'}> ({key})",
+                     "kernel": f"me_kernel<{'double' if prec == M.FP64 else 'float'}> ({key}, {a.precision})",
                      "flops_per_launch": flops},
     }
     if not a.no_cpu_baseline:

@@ -15,7 +15,8 @@
  *    describing the last failure on the calling thread.
  *  - Device pointers (d_*) are owned by the caller (for example
  *    torch.Tensor.data_ptr() of a CUDA/HIP tensor); the library never frees
- *    or retains them.  A process owns only its own host state.
+ *    or retains them.  A process owns its host state and one small device
+ *    table (the colour matrix in matrix-core operand layout).
  *  - Kernels are enqueued asynchronously on `hip_stream` (a hipStream_t; NULL
  *    is the default stream).  Nothing synchronises; an asynchronous device
  *    fault is reported as MGME_EDEVICE by the next call.
@@ -45,7 +46,8 @@ typedef enum {
   MGME_FP64 = 0, /* plain method: every step in double precision */
   MGME_FP32 = 1, /* diagrams in single precision; momenta, propagator denominators,
                     colour quadratic form and helicity sum in double */
-  MGME_MIXED = 2 /* single-precision diagrams with a 16-bit matrix-core colour sum (not yet available) */
+  MGME_MIXED = 2 /* single-precision diagrams; colour sum on the matrix cores with J split into two
+                    power-of-two-scaled half-precision parts (FP32 accumulation); helicity sum in double */
 } mgme_precision;
 
 /* Couplings and masses.  alpha_s is fixed (no running).  The top width wt
@@ -80,7 +82,8 @@ typedef struct mgme_process mgme_process;
  * good helicities: every helicity configuration is evaluated in FP64 on 64
  * RAMBO events (seed 1, sqrt(s) = 500 GeV for e+e- and 1500 GeV otherwise);
  * a helicity is kept if its contribution is non-zero on at least one event.
- * The process keeps no device memory.  Thread-safe.
+ * The process keeps a few kilobytes of device memory (the colour matrix in
+ * matrix-core operand layout), released by mgme_process_destroy.  Thread-safe.
  * Errors: EINVAL (NULL pointer, n_in != 2, non-finite or non-positive
  * couplings/masses), EUNSUPPORTED (other particles, wt != 0), EDEVICE. */
 int mgme_process_create(int n_in, int n_out, const int* pdg, const mgme_params* params, int device,
@@ -114,9 +117,18 @@ int mgme_rambo(const mgme_process* proc, double sqrt_s, unsigned long long seed,
 
 /* |M|^2 per event, summed over the good helicities and all colours and
  * normalised by norm_factor, into d_me[nevt] (FP64 in every precision).
- * Errors: EINVAL, EUNSUPPORTED (MGME_MIXED), EDEVICE. */
+ * Processes with many colour flows (g g -> t t~ g g g), and MGME_MIXED for
+ * every process, stage colour-flow amplitudes in a workspace taken from the
+ * stream-ordered allocator (hipMallocAsync) and returned at the end of the
+ * call (at most a few GB, on `hip_stream`).
+ * Errors: EINVAL, EDEVICE (also when the workspace cannot be allocated). */
 int mgme_matrix_element(const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
                         int precision, double* d_me, void* hip_stream);
+
+/* Device workspace (bytes) that mgme_matrix_element takes from the
+ * stream-ordered allocator for a batch of nevt events in `precision`
+ * (0 when the process needs none). */
+int mgme_workspace_bytes(const mgme_process* proc, long long nevt, int precision, long long* bytes);
 
 /* Per-helicity contributions of every one of the n_hel helicity
  * configurations (not only the good ones), normalised like
@@ -125,6 +137,53 @@ int mgme_matrix_element_per_helicity(const mgme_process* proc, const double* d_m
                                      int precision, double* d_out, long long ldo, void* hip_stream);
 
 const char* mgme_last_error(void);
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of requests of different processes, precisions and
+ * sizes on one GPU (the paper's observation that several clients sharing a
+ * GPU raise its combined throughput, section 2, Fig. 1).  Requests are queued
+ * on submission; a scheduler thread admits them in arrival order onto free
+ * slots (one stream each) whenever the summed device workspace of the running
+ * requests stays within the budget (see mgme_workspace_bytes), passing over a
+ * request that does not fit in favour of a later one that does; a request
+ * larger than the whole budget runs alone.  Admitted requests run
+ * concurrently.  Each request runs exactly the kernels of a standalone
+ * mgme_matrix_element call, so its result does not depend on the others. */
+typedef struct mgme_server mgme_server;
+
+typedef struct {
+  int n_slots;                  /* requests running at once (1..64) */
+  long long hbm_budget_bytes;   /* bound on the summed workspace of running requests */
+  int fake_executor;            /* 1: test double, no device work: a request completes
+                                   fake_ns_per_event * nevt ns after admission, footprint
+                                   fake_bytes_per_event * nevt; process and device pointers unused */
+  double fake_ns_per_event;
+  long long fake_bytes_per_event;
+} mgme_server_config;
+
+typedef struct {
+  long long submitted, completed, failed, events;
+  double p50_ms, p99_ms, mean_ms, max_ms; /* submission-to-completion latency of completed requests */
+  double wall_s;                          /* first submission to last completion */
+  int max_concurrent;                     /* most requests running at once */
+  long long peak_workspace_bytes;         /* largest summed workspace of running requests */
+} mgme_server_stats;
+
+int mgme_server_create(const mgme_server_config* cfg, int device, mgme_server** out);
+/* Queues |M|^2 of one batch (arguments as mgme_matrix_element; every pointer
+ * must stay valid, and the process alive, until the request completes).
+ * *id identifies the request for mgme_server_wait. */
+int mgme_server_submit(mgme_server* s, const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
+                       int precision, double* d_me, unsigned long long* id);
+/* Blocks until request `id` completed; returns its status and releases it
+ * (each request is waited for at most once). */
+int mgme_server_wait(mgme_server* s, unsigned long long id, double* latency_ms);
+/* Blocks until no request is queued or running. */
+int mgme_server_drain(mgme_server* s);
+int mgme_server_get_stats(mgme_server* s, mgme_server_stats* out);
+/* Runs every queued request to completion, then releases the server. */
+int mgme_server_destroy(mgme_server* s);
+const char* mgme_server_last_error(void);
 
 #ifdef __cplusplus
 }

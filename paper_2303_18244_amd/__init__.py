@@ -31,7 +31,24 @@ DEFAULT_PARAMS = dict(alpha_s=0.118, alpha_em=1.0 / 132.5, sin2w=0.2222, mz=91.1
 # Entry points declared in include/mgme.h.
 EXPORTS = ["mgme_process_create", "mgme_process_destroy", "mgme_process_info", "mgme_good_helicities",
            "mgme_colour_matrix", "mgme_rambo", "mgme_matrix_element", "mgme_matrix_element_per_helicity",
-           "mgme_last_error"]
+           "mgme_workspace_bytes", "mgme_last_error", "mgme_server_create", "mgme_server_submit",
+           "mgme_server_wait", "mgme_server_drain", "mgme_server_get_stats", "mgme_server_destroy",
+           "mgme_server_last_error"]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_longlong), ("fake_executor", ctypes.c_int),
+                ("fake_ns_per_event", ctypes.c_double), ("fake_bytes_per_event", ctypes.c_longlong)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong), ("failed", ctypes.c_longlong),
+                ("events", ctypes.c_longlong), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("wall_s", ctypes.c_double),
+                ("max_concurrent", ctypes.c_int), ("peak_workspace_bytes", ctypes.c_longlong)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class MgmeError(RuntimeError):
@@ -78,9 +95,17 @@ def lib() -> ctypes.CDLL:
         L.mgme_rambo.argtypes = [vp, ctypes.c_double, u64, u64, i64, i64, dp, dp, vp]
         L.mgme_matrix_element.argtypes = [vp, dp, i64, i64, ctypes.c_int, dp, vp]
         L.mgme_matrix_element_per_helicity.argtypes = [vp, dp, i64, i64, ctypes.c_int, dp, i64, vp]
+        L.mgme_workspace_bytes.argtypes = [vp, i64, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
+        L.mgme_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.c_int, ctypes.POINTER(vp)]
+        L.mgme_server_submit.argtypes = [vp, vp, dp, i64, i64, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_ulonglong)]
+        L.mgme_server_wait.argtypes = [vp, ctypes.c_ulonglong, ctypes.POINTER(ctypes.c_double)]
+        L.mgme_server_drain.argtypes = [vp]
+        L.mgme_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+        L.mgme_server_destroy.argtypes = [vp]
         L.mgme_last_error.restype = ctypes.c_char_p
+        L.mgme_server_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name != "mgme_last_error":
+            if not name.endswith("last_error"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -89,6 +114,11 @@ def lib() -> ctypes.CDLL:
 def _check(rc: int) -> None:
     if rc != MGME_OK:
         raise MgmeError(rc, lib().mgme_last_error().decode())
+
+
+def _scheck(rc: int) -> None:
+    if rc != MGME_OK:
+        raise MgmeError(rc, lib().mgme_server_last_error().decode())
 
 
 def _stream_handle(stream) -> Optional[int]:
@@ -179,3 +209,61 @@ class Process:
                                                       int(precision), out.data_ptr(), int(out.shape[1]),
                                                       _stream_handle(stream)))
         return out[:, :nevt]
+
+
+class Server:
+    """Continuous-batching request loop on one GPU (see mgme_server_* in
+    include/mgme.h).  Tensors passed to submit() are kept referenced until
+    their request has been waited for."""
+
+    def __init__(self, n_slots: int = 4, hbm_budget_bytes: int = 32 << 30, device: int = 0,
+                 fake_ns_per_event: Optional[float] = None, fake_bytes_per_event: int = 0):
+        cfg = ServerConfig(n_slots, hbm_budget_bytes, 1 if fake_ns_per_event is not None else 0,
+                           float(fake_ns_per_event or 0.0), int(fake_bytes_per_event))
+        self._h = ctypes.c_void_p()
+        _scheck(lib().mgme_server_create(ctypes.byref(cfg), device, ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit(self, proc: Optional[Process], mom=None, nevt: Optional[int] = None, precision: int = FP64,
+               out=None) -> int:
+        """Queues one batch; returns the request id.  With the test double,
+        proc, mom and out may be None (only nevt is used)."""
+        rid = ctypes.c_ulonglong()
+        if mom is None:
+            _scheck(lib().mgme_server_submit(self._h, None, None, int(nevt), int(nevt), int(precision), None,
+                                             ctypes.byref(rid)))
+            return rid.value
+        ld = mom.shape[-1]
+        nevt = ld if nevt is None else nevt
+        _scheck(lib().mgme_server_submit(self._h, proc._h, mom.data_ptr(), int(nevt), int(ld), int(precision),
+                                         out.data_ptr(), ctypes.byref(rid)))
+        self._keep[rid.value] = (proc, mom, out)
+        return rid.value
+
+    def wait(self, rid: int) -> float:
+        """Blocks until the request completed; returns its latency in ms."""
+        lat = ctypes.c_double()
+        rc = lib().mgme_server_wait(self._h, rid, ctypes.byref(lat))
+        self._keep.pop(rid, None)
+        _scheck(rc)
+        return lat.value
+
+    def drain(self) -> None:
+        _scheck(lib().mgme_server_drain(self._h))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _scheck(lib().mgme_server_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            lib().mgme_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -197,11 +197,10 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
         body.amplitude(a)
         upd = " ".join(f"acc(J[{f}], a, {re}, {im});" for f, re, im in a.coeffs)
         em.w(f"  {upd} }}")
-    em.w("double me = 0.0;")
-    for line in colour_sum_lines(C, cden):
-        em.w(line)
+    colour = ["      double me = 0.0;"] + ["  " + ln for ln in colour_sum_lines(C, cden)]
     flops_hel = sched.flops_per_helicity() + 2 * ncol * ncol + 4 * ncol + 90 * n_ext
-    return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "\n".join(em.lines))
+    return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "\n".join(em.lines),
+                    colour="\n".join(colour))
 
 
 def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefetch: int = 6) -> Dict:
@@ -328,10 +327,10 @@ def emit_ee_process(name: str, pdg: List[int]) -> Dict:
     w("  const cx<T> prop = mk<T>((T)(args.ee_zz * dr * dn), (T)(-args.ee_zz * di * dn));")
     w("  J[0] = J[0] + prop * mdot(zl, zm);")
     w("}")
-    w("double me = (double)J[0].re * (double)J[0].re + (double)J[0].im * (double)J[0].im;")
     meta = dict(name=name, pdg=pdg, n_ext=4, n_diagrams=2, n_terms=2, ncol=1, cden=1, n_currents=4,
                 n_amps=2, gs_power=0, spin_colour_avg=4, ident=1, kind="ee",
-                flops_per_hel=2 * 128 + 2 * 30 + 20, flops_per_event=40, body="\n".join(lines))
+                flops_per_hel=2 * 128 + 2 * 30 + 20, flops_per_event=40, body="\n".join(lines),
+                colour="      double me = (double)J[0].re * (double)J[0].re + (double)J[0].im * (double)J[0].im;")
     return meta
 
 
@@ -340,16 +339,23 @@ KERNEL_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}.
 // {n_currents} shared off-shell currents and {n_amps} amplitude vertices per helicity.
 #include "../helamp.h"
 #include "../me_kernel.h"
+#include "../colour_mfma.h"
 
 namespace mgme {{
 namespace {name} {{
 
 constexpr int NEXT = {n_ext};
+constexpr int NCOL = {ncol};
 
-template <typename T, bool PER_HEL>
+// MODE 0: |M|^2 summed over the good helicities into out[e];
+// MODE 1: each helicity's contribution into out[ih*ldo + e];
+// MODE 2: the colour-flow vector J of every helicity into
+//         Jout[(ih*NCOL + s)*ldo + e] (single precision) for the matrix-core colour sum.
+template <typename T, int MODE>
 __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restrict__ mom, long long nevt,
                                                           long long ld, const MeArgs args,
-                                                          double* __restrict__ out, long long ldo) {{
+                                                          double* __restrict__ out, long long ldo,
+                                                          float2* __restrict__ Jout) {{
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nevt) return;
   double p[NEXT][4];
@@ -372,10 +378,17 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
         asm volatile("" : "+v"(q[i][mu]));
       }}
 {body}
-    if (PER_HEL) out[(long long)ih * ldo + e] = me * args.factor;
-    else total += me;
+    if constexpr (MODE == 2) {{
+#pragma unroll
+      for (int s = 0; s < NCOL; ++s)
+        Jout[((long long)ih * NCOL + s) * ldo + e] = make_float2((float)J[s].re, (float)J[s].im);
+    }} else {{
+{colour}
+      if (MODE == 1) out[(long long)ih * ldo + e] = me * args.factor;
+      else total += me;
+    }}
   }}
-  if (!PER_HEL) out[e] = total * args.factor;
+  if (MODE == 0) out[e] = total * args.factor;
 }}
 
 }}  // namespace {name}
@@ -384,14 +397,41 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
 extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                           const mgme::MeArgs* args, double* out, long long ldo,
                                           hipStream_t stream) {{
+  using namespace mgme::{name};
   const dim3 block(MGME_ME_BLOCK);
+  if (prec == 2) {{
+    // single-precision diagrams write J, the matrix cores form the colour sum
+    const int nh = args->nhel;
+    const size_t per_event = (size_t)nh * (NCOL * sizeof(float2) + sizeof(double));
+    long long sub = (long long)(((size_t)4 << 30) / per_event) / 64 * 64;
+    if (sub < 64) sub = 64;
+    if (sub > nevt) sub = (nevt + 63) / 64 * 64;
+    char* ws = nullptr;
+    hipError_t err = hipMallocAsync((void**)&ws, per_event * (size_t)sub, stream);
+    if (err != hipSuccess) return err;
+    float2* J = (float2*)ws;
+    double* meh = (double*)(ws + (size_t)nh * NCOL * sizeof(float2) * sub);
+    for (long long start = 0; start < nevt && err == hipSuccess; start += sub) {{
+      const long long n = (nevt - start < sub) ? nevt - start : sub;
+      const dim3 grid((unsigned)((n + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
+      me_kernel<float, 2><<<grid, block, 0, stream>>>(mom + start, n, ld, *args, nullptr, sub, J);
+      err = hipGetLastError();
+      if (err == hipSuccess)
+        err = mgme::launch_colour_mfma(n, nh, NCOL, J, sub, args->cfrag, per_hel ? out + start : meh,
+                                       per_hel ? ldo : sub, per_hel ? args->factor : 1.0, stream);
+      if (err == hipSuccess && !per_hel)
+        err = mgme::launch_helicity_sum(n, nh, meh, sub, args->factor, out + start, stream);
+    }}
+    const hipError_t ferr = hipFreeAsync(ws, stream);
+    return err != hipSuccess ? err : ferr;
+  }}
   const dim3 grid((unsigned)((nevt + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
   if (prec == 0) {{
-    if (per_hel) mgme::{name}::me_kernel<double, true><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo);
-    else mgme::{name}::me_kernel<double, false><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo);
+    if (per_hel) me_kernel<double, 1><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
+    else me_kernel<double, 0><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
   }} else {{
-    if (per_hel) mgme::{name}::me_kernel<float, true><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo);
-    else mgme::{name}::me_kernel<float, false><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo);
+    if (per_hel) me_kernel<float, 1><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
+    else me_kernel<float, 0><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
   }}
   return hipGetLastError();
 }}
@@ -460,6 +500,7 @@ COLOUR_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: 
 // ({n_rmw} read-modify-write folds and {n_overflow} overflow slots per (event, helicity)).
 #include "../helamp.h"
 #include "../me_kernel.h"
+#include "../colour_mfma.h"
 
 namespace mgme {{
 namespace {name} {{
@@ -509,14 +550,17 @@ __global__ void __launch_bounds__(256) colour_kernel(long long nevt, const MeArg
   out[(long long)hs * ldo + e] = me * scale;
 }}
 
-// out[e] = factor * sum over helicities of me_h[e], in helicity order.
-__global__ void __launch_bounds__(256) helicity_sum_kernel(long long nevt, int nhel, const double* __restrict__ meh,
-                                                          long long ldh, double factor, double* __restrict__ out) {{
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nevt) return;
-  double s = 0.0;
-  for (int h = 0; h < nhel; ++h) s += meh[(long long)h * ldh + e];
-  out[e] = s * factor;
+// Adds the overflow slots into J (mixed precision: before the matrix-core colour sum).
+template <typename T>
+__global__ void __launch_bounds__(256) fold_kernel(long long nevt, const MeArgs args, cx<T>* __restrict__ Jbuf,
+                                                  const cx<T>* __restrict__ Ovbuf, long long ldp) {{
+  const int hs = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (threadIdx.x >> 6));
+  const long long e = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
+  if (hs >= args.nhel || e >= nevt) return;
+  cx<T>* __restrict__ J = Jbuf + (long long)hs * NCOL * ldp + e;
+  const cx<T>* __restrict__ Ov = Ovbuf + (long long)hs * NOV * ldp + e;
+  (void)Ov;
+{overflow_sums}
 }}
 
 }}  // namespace {name}
@@ -531,7 +575,8 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
                                           hipStream_t stream) {{
   using namespace mgme::{name};
   const int nh = args->nhel;
-  const size_t tsize = prec == 0 ? sizeof(mgme::cx<double>) : sizeof(mgme::cx<float>);
+  const int dprec = prec == 0 ? 0 : 1;  // diagram precision
+  const size_t tsize = dprec == 0 ? sizeof(mgme::cx<double>) : sizeof(mgme::cx<float>);
   const size_t per_event = (size_t)nh * ((NCOL + NOV) * tsize + sizeof(double));
   const size_t budget = (size_t){workspace_bytes};
   long long sub = (long long)(budget / per_event) / 64 * 64;
@@ -554,15 +599,21 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
     double* dst = per_hel ? out + start : meh;
     const long long ldd = per_hel ? ldo : sub;
     const double sc = per_hel ? factor : 1.0;
-    if (prec == 0)
+    if (prec == 0) {{
       colour_kernel<double><<<grid, 256, 0, stream>>>(n, *args, (mgme::cx<double>*)Jbuf,
                                                      (const mgme::cx<double>*)Ovbuf, sub, dst, ldd, sc);
-    else
+    }} else if (prec == 1) {{
       colour_kernel<float><<<grid, 256, 0, stream>>>(n, *args, (mgme::cx<float>*)Jbuf,
                                                     (const mgme::cx<float>*)Ovbuf, sub, dst, ldd, sc);
-    if (!per_hel)
-      helicity_sum_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(n, nh, meh, sub, factor, out + start);
-    err = hipGetLastError();
+    }} else {{
+      fold_kernel<float><<<grid, 256, 0, stream>>>(n, *args, (mgme::cx<float>*)Jbuf,
+                                                  (const mgme::cx<float>*)Ovbuf, sub);
+      err = hipGetLastError();
+      if (err == hipSuccess)
+        err = mgme::launch_colour_mfma(n, nh, NCOL, Jbuf, sub, args->cfrag, dst, ldd, sc, stream);
+    }}
+    if (err == hipSuccess) err = hipGetLastError();
+    if (err == hipSuccess && !per_hel) err = mgme::launch_helicity_sum(n, nh, meh, sub, factor, out + start, stream);
   }}
   const hipError_t ferr = hipFreeAsync(ws, stream);
   return err != hipSuccess ? err : ferr;
@@ -591,7 +642,7 @@ def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 1
         f'extern "C" hipError_t mgme_{meta["name"]}_chunk{c}(int, dim3, const double*, long long, long long, '
         f'const mgme::MeArgs*, void*, void*, long long, hipStream_t);' for c in range(nchunk))
     calls = "\n".join(
-        f"    if (err == hipSuccess) err = mgme_{meta['name']}_chunk{c}(prec, grid, mom + start, n, ld, args, "
+        f"    if (err == hipSuccess) err = mgme_{meta['name']}_chunk{c}(dprec, grid, mom + start, n, ld, args, "
         f"Jbuf, Ovbuf, sub, stream);" for c in range(nchunk))
     assert meta["ncol"] % nb == 0
     out[f"me_{meta['name']}.hip"] = COLOUR_TEMPLATE.format(

@@ -21,10 +21,12 @@ struct MeArgs {
   double ee_gr;     // -Q sw^2
   double mz, wz;
   int z_enabled;
+  const void* cfrag;        // colour matrix as half-precision MFMA A fragments (mixed precision)
   int nhel;                 // helicities to sum
   int hel[MGME_MAX_HEL];    // helicity codes: bit (n_ext-1-leg) set for helicity +1
 };
 
+// prec: 0 FP64, 1 FP32 diagrams, 2 FP32 diagrams + 16-bit matrix-core colour sum.
 using LaunchFn = hipError_t (*)(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                 const MeArgs* args, double* out, long long ldo, hipStream_t stream);
 

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "colour_mfma.h"
 #include "me_kernel.h"
 #include "rambo.h"
 #include "registry.h"
@@ -24,6 +25,7 @@ struct mgme_process {
   double mass_out[6];
   double norm_factor;
   double gs;
+  void* d_cfrag;          // colour matrix as half-precision MFMA fragments (device)
 };
 
 namespace {
@@ -153,7 +155,43 @@ int check_batch(const mgme_process* proc, const void* a, const void* b, long lon
 
 }  // namespace
 
+namespace mgme {
+
+// Workspace bounds of the generated launchers: staged processes take up to
+// 12 GB (at most 16384 events per sub-batch), the mixed-precision path of the
+// other processes up to 4 GB.
+long long workspace_bytes(const ProcEntry& e, int nhel, long long nevt, int prec) {
+  if (nevt <= 0) return 0;
+  const long long round64 = (nevt + 63) / 64 * 64;
+  if (e.staged) {
+    const long long tsize = prec == 0 ? 16 : 8;
+    const long long per_event = (long long)nhel * ((e.n_colour + e.n_overflow) * tsize + 8);
+    long long sub = (12ll << 30) / per_event / 64 * 64;
+    if (sub < 64) sub = 64;
+    if (sub > 16384) sub = 16384;
+    if (sub > round64) sub = round64;
+    return per_event * sub;
+  }
+  if (prec == 2) {
+    const long long per_event = (long long)nhel * (e.n_colour * 8 + 8);
+    long long sub = (4ll << 30) / per_event / 64 * 64;
+    if (sub < 64) sub = 64;
+    if (sub > round64) sub = round64;
+    return per_event * sub;
+  }
+  return 0;
+}
+
+}  // namespace mgme
+
 extern "C" {
+
+int mgme_workspace_bytes(const mgme_process* proc, long long nevt, int precision, long long* bytes) {
+  if (!proc || !bytes || nevt < 0) return fail(MGME_EINVAL, "bad argument");
+  if (precision < MGME_FP64 || precision > MGME_MIXED) return fail(MGME_EINVAL, "unknown precision");
+  *bytes = mgme::workspace_bytes(*proc->entry, proc->args.nhel, nevt, precision);
+  return MGME_OK;
+}
 
 const char* mgme_last_error(void) { return g_error.c_str(); }
 
@@ -205,8 +243,31 @@ int mgme_process_create(int n_in, int n_out, const int* pdg, const mgme_params* 
     p->args.wz = P.wz;
     p->args.z_enabled = P.z_enabled ? 1 : 0;
   }
+  // colour matrix fragments for the matrix-core colour sum
+  {
+    int mt = 0, ks = 0;
+    if (mgme::colour_mfma_tiles(entry->n_colour, &mt, &ks) != 0) {
+      delete p;
+      return fail(MGME_EUNSUPPORTED, "too many colour flows");
+    }
+    std::vector<unsigned short> frag((size_t)mt * ks * 64 * 8);
+    mgme::colour_mfma_fragments(entry->n_colour, entry->colour_num, frag.data());
+    he = hipMalloc(&p->d_cfrag, frag.size() * sizeof(unsigned short));
+    if (he != hipSuccess) {
+      delete p;
+      return fail(MGME_ENOMEM, "colour fragments");
+    }
+    he = hipMemcpy(p->d_cfrag, frag.data(), frag.size() * sizeof(unsigned short), hipMemcpyHostToDevice);
+    if (he != hipSuccess) {
+      (void)hipFree(p->d_cfrag);
+      delete p;
+      return hip_fail(he, "colour fragments");
+    }
+    p->args.cfrag = p->d_cfrag;
+  }
   rc = calibrate(p);
   if (rc != MGME_OK) {
+    (void)hipFree(p->d_cfrag);
     delete p;
     return rc;
   }
@@ -215,6 +276,17 @@ int mgme_process_create(int n_in, int n_out, const int* pdg, const mgme_params* 
 }
 
 int mgme_process_destroy(mgme_process* proc) {
+  if (!proc) return MGME_OK;
+  if (proc->d_cfrag) {
+    int rc = select_device(proc->device);
+    if (rc != MGME_OK) return rc;
+    const hipError_t e = hipFree(proc->d_cfrag);
+    proc->d_cfrag = nullptr;
+    if (e != hipSuccess) {
+      delete proc;
+      return hip_fail(e, "hipFree");
+    }
+  }
   delete proc;
   return MGME_OK;
 }
@@ -268,8 +340,8 @@ int mgme_matrix_element(const mgme_process* proc, const double* d_mom, long long
                         double* d_me, void* hip_stream) {
   int rc = check_batch(proc, d_mom, d_me, nevt, ld);
   if (rc != MGME_OK) return rc;
-  if (precision == MGME_MIXED) return fail(MGME_EUNSUPPORTED, "mixed precision is not available");
-  if (precision != MGME_FP64 && precision != MGME_FP32) return fail(MGME_EINVAL, "unknown precision");
+  if (precision != MGME_FP64 && precision != MGME_FP32 && precision != MGME_MIXED)
+    return fail(MGME_EINVAL, "unknown precision");
   if ((rc = check_pending("mgme_matrix_element")) != MGME_OK) return rc;
   if (nevt == 0) return MGME_OK;
   if ((rc = select_device(proc->device)) != MGME_OK) return rc;
@@ -284,7 +356,8 @@ int mgme_matrix_element_per_helicity(const mgme_process* proc, const double* d_m
   int rc = check_batch(proc, d_mom, d_out, nevt, ld);
   if (rc != MGME_OK) return rc;
   if (ldo < nevt) return fail(MGME_EINVAL, "ldo < nevt");
-  if (precision != MGME_FP64 && precision != MGME_FP32) return fail(MGME_EINVAL, "unknown precision");
+  if (precision != MGME_FP64 && precision != MGME_FP32 && precision != MGME_MIXED)
+    return fail(MGME_EINVAL, "unknown precision");
   if ((rc = check_pending("mgme_matrix_element_per_helicity")) != MGME_OK) return rc;
   if (nevt == 0) return MGME_OK;
   if ((rc = select_device(proc->device)) != MGME_OK) return rc;

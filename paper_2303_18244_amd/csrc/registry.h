@@ -23,7 +23,13 @@ struct ProcEntry {
   const long long* colour_num;  // n_colour^2 numerators
   const int* basis;             // n_colour x n_gluons legs
   int n_gluons;
+  int staged;                   // colour-flow vector staged in device memory (many flows)
+  int n_overflow;               // staged: overflow slots per (event, helicity)
 };
+
+// Device workspace one mgme_matrix_element call takes from the stream-ordered
+// allocator (mirrors the sub-batching of the launchers).
+long long workspace_bytes(const ProcEntry& e, int nhel, long long nevt, int prec);
 
 extern const ProcEntry kProcesses[];
 extern const int kNumProcesses;

@@ -126,6 +126,25 @@ def test_fp32_accuracy(lib_procs, oracle_procs, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+def test_mixed_accuracy(lib_procs, oracle_procs, name):
+    """Single-precision diagrams with the 16-bit matrix-core colour sum."""
+    torch = _torch()
+    import paper_2303_18244_amd as M
+
+    P = _proc(lib_procs, name)
+    n, _, sq = CASES[name]
+    mom, _ = P.rambo(sq, SEED, 0, n)
+    me = P.matrix_element(mom, precision=M.MIXED).cpu().numpy()
+    ref = oracle_procs[name].me(_host(mom, n), nthreads=NTHREADS)
+    rel = np.abs(me / ref - 1.0)
+    mean_rel = abs(me.mean() / ref.mean() - 1.0)
+    print(f"{name} mixed vs oracle on {n} events: batch-mean {mean_rel:.2e}, median {np.median(rel):.2e}, "
+          f"p99 {np.quantile(rel, 0.99):.2e}, max {rel.max():.2e}")
+    assert mean_rel <= 1e-5
+    assert np.median(rel) <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(CASES))
 def test_full_size_sampled(lib_procs, oracle_procs, name):
     """The configuration's full batch in one launch: sampled events against the
     oracle, and the leading events bitwise equal to a small batch (no
@@ -224,11 +243,31 @@ def test_determinism_and_ragged_edges(lib_procs):
     P.matrix_element(padded, nevt=0, out=out0)
     assert np.all(out0.cpu().numpy() == -3.0)
     with pytest.raises(M.MgmeError) as ei:
-        P.matrix_element(mom, precision=M.MIXED)
-    assert ei.value.code == M.MGME_EUNSUPPORTED
-    with pytest.raises(M.MgmeError) as ei:
         P.matrix_element(mom, precision=7)
     assert ei.value.code == M.MGME_EINVAL
+
+
+@pytest.mark.parametrize("name", ["gg_ttgg", "gg_ttggg"])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_staging_edges(lib_procs, name, prec):
+    """Ragged batch sizes, a padded leading dimension and batches spanning
+    several sub-batches of the staging buffers give the same per-event values
+    as one small batch."""
+    torch = _torch()
+    P = _proc(lib_procs, name)
+    n = 200
+    mom, _ = P.rambo(1500.0, SEED, 0, n)
+    a = P.matrix_element(mom, precision=prec).cpu().numpy()
+    for m in (1, 63, 65, 131):
+        b = P.matrix_element(mom[:, :, :m].contiguous(), precision=prec).cpu().numpy()
+        np.testing.assert_array_equal(b, a[:m])
+    padded = torch.zeros((P.n_ext, 4, 256), dtype=torch.float64, device="cuda")
+    padded[:, :, :n] = mom
+    out = torch.full((256,), -5.0, dtype=torch.float64, device="cuda")
+    P.matrix_element(padded, nevt=n, precision=prec, out=out)
+    o = out.cpu().numpy()
+    np.testing.assert_array_equal(o[:n], a)
+    assert np.all(o[n:] == -5.0)
 
 
 def test_colour_matrix_export_matches_oracle(lib_procs, oracle_procs):
