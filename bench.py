@@ -33,6 +33,12 @@ WORKLOADS = {
 SEED = 230318244
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 FP32_VALU_PEAK_TFLOPS = 78.6   # the same lanes without packed FP32 instructions
+# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs (KiB per dispatch), valid only for the kernels identified by
+# kernel_hash; each counter is scaled by what it reads for a plain
+# device-to-device copy of known size (FETCH_SIZE reports half the bytes
+# read on this GPU, WRITE_SIZE all of them).
+TRAFFIC = {}
 # The paper's standalone CUDA throughput on one V100 for this workload
 # (g g -> t t~ g g, double, grid 524288): 4.21E5 MEs/s.
 PAPER_MES = {("gg_ttgg", 0): 4.21e5, ("gg_ttgg", 1): 8.77e5}
@@ -60,6 +66,67 @@ def cpu_baseline(name: str, n_events: int, mom_host, seconds: float = 12.0):
                       f"{threads} threads, {wall:.1f} s wall"}
 
 
+def serve_bench(n_requests: int, rho: float, slots: int, seed: int = 7) -> dict:
+    """Serving mix: requests for g g -> t t~ (+0..3 g), log-uniform batch
+    sizes 1024..524288 events, FP64 or mixed precision with equal odds,
+    Poisson arrivals at rho times the capacity measured by running the same
+    requests one at a time.  Returns latency percentiles and throughput."""
+    import numpy as np
+    import torch
+
+    import paper_2303_18244_amd as M
+
+    rng = np.random.default_rng(seed)
+    names = ["gg_tt", "gg_ttg", "gg_ttgg", "gg_ttggg"]
+    procs = {n: M.Process(M.PROCESSES[n]) for n in names}
+    plan = []
+    for k in range(n_requests):
+        name = names[rng.integers(len(names))]
+        n = int(np.exp(rng.uniform(np.log(1024), np.log(524288))))
+        prec = M.FP64 if rng.random() < 0.5 else M.MIXED
+        plan.append((name, n, prec))
+    moms = []
+    for k, (name, n, prec) in enumerate(plan):
+        mom, _ = procs[name].rambo(1500.0, SEED, k << 20, n)  # request k: events of its own counter range
+        moms.append(mom)
+    outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _, n, _ in plan]
+    torch.cuda.synchronize()
+    # capacity: the same requests back to back, one at a time
+    alone_ms = []
+    for (name, n, prec), mom, out in zip(plan, moms, outs):
+        t0 = time.perf_counter()
+        procs[name].matrix_element(mom, precision=prec, out=out)
+        torch.cuda.synchronize()
+        alone_ms.append((time.perf_counter() - t0) * 1e3)
+    mean_service = float(np.mean(alone_ms)) * 1e-3
+    rate = rho / mean_service
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    S = M.Server(n_slots=slots, hbm_budget_bytes=48 << 30)
+    t0 = time.perf_counter()
+    due = t0
+    ids = []
+    for (name, n, prec), mom, out, gap in zip(plan, moms, outs, gaps):
+        due += gap
+        while time.perf_counter() < due:
+            time.sleep(min(0.001, max(0.0, due - time.perf_counter())))
+        ids.append(S.submit(procs[name], mom, precision=prec, out=out))
+    for i in ids:
+        S.wait(i)
+    wall = time.perf_counter() - t0
+    st = S.stats()
+    S.close()
+    events = sum(n for _, n, _ in plan)
+    return {"metric": "serving mix: latency p50/p99 and MEs/s", "value": events / st["wall_s"],
+            "unit": "MEs/s", "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+            "max_ms": st["max_ms"], "requests": n_requests, "events": events, "offered_load": rho,
+            "slots": slots, "max_concurrent": st["max_concurrent"],
+            "alone_p50_ms": float(np.median(alone_ms)), "alone_p99_ms": float(np.quantile(alone_ms, 0.99)),
+            "alone_mes_per_s": events / (sum(alone_ms) * 1e-3), "wall_s": wall,
+            "config": {"workload": "serving mix gg->tt+0..3g, sizes log-uniform 1024..524288, FP64/mixed 50/50",
+                       "arrivals": f"Poisson, rate {rate:.2f}/s", "seed": seed},
+            "data": "synthetic (RAMBO flat phase space)"}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +135,10 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="gg_ttgg", choices=list(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="instead of the benchmark, run the serving mix with N requests")
+    ap.add_argument("--rho", type=float, default=0.8)
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="instead of the benchmark, time a plain device-to-device copy of this many bytes "
                          "(the reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -79,6 +150,10 @@ def main(argv=None) -> int:
 
     import numpy as np
     import torch
+
+    if a.serve:
+        print(json.dumps(serve_bench(a.serve, a.rho, a.slots)), flush=True)
+        return 0
 
     if a.copy_bytes:
         n = a.copy_bytes // 8
@@ -130,6 +205,10 @@ def main(argv=None) -> int:
     flops = (info["flops_per_hel"] * ngood + info["flops_per_event"]) * nevt
     achieved = flops / (me_ms * 1e-3) * 1e-12
     peak = FP64_VALU_PEAK_TFLOPS if prec == M.FP64 else FP32_VALU_PEAK_TFLOPS
+    tr = TRAFFIC.get((key, a.precision))
+    traffic = None
+    if tr is not None and tr["kernel_hash"] == info["kernel_hash"]:
+        traffic = (tr["fetch_kib"] * tr["fetch_scale"] + tr["write_kib"] * tr["write_scale"]) * 1024.0
     assert bool(torch.isfinite(me).all()), "non-finite matrix element"
 
     result = {
@@ -147,10 +226,10 @@ def main(argv=None) -> int:
         "data": "synthetic (RAMBO flat phase space, Philox seed 230318244)",
         "config": {"workload": key, "events_per_batch": nevt, "sqrt_s_gev": sqrt_s,
                    "precision": a.precision, "good_helicities": ngood, "diagrams": info["n_diagrams"],
-                   "colour_flows": info["n_colour"]},
+                   "colour_flows": info["n_colour"], "kernel_hash": str(info["kernel_hash"])},
         "me_only": {"ms_per_launch": me_ms, "mes_per_s": nevt / (me_ms * 1e-3)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "kernel": f"me_kernel<{'double' if prec == M.FP64 else 'float'}> ({key}, {a.precision})",
                      "flops_per_launch": flops},
     }

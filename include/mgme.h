@@ -70,6 +70,7 @@ typedef struct {
   double norm_factor;     /* 1 / (initial spin-colour average * final identical-particle factor) */
   double flops_per_hel;   /* floating-point operations per event and good helicity (static tally) */
   double flops_per_event; /* helicity-independent operations per event */
+  unsigned long long kernel_hash; /* identifies the generated kernels (changes whenever they change) */
 } mgme_info;
 
 typedef struct mgme_process mgme_process;

@@ -68,7 +68,7 @@ class Info(ctypes.Structure):
                 ("n_colour", ctypes.c_int), ("n_hel", ctypes.c_int), ("n_good_hel", ctypes.c_int),
                 ("n_currents", ctypes.c_int), ("n_amp_vertices", ctypes.c_int),
                 ("norm_factor", ctypes.c_double), ("flops_per_hel", ctypes.c_double),
-                ("flops_per_event", ctypes.c_double)]
+                ("flops_per_event", ctypes.c_double), ("kernel_hash", ctypes.c_ulonglong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

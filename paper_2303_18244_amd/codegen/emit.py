@@ -95,18 +95,17 @@ class GGBody:
             lam = f"((hc >> {n_ext - 1 - i}) & 1 ? 1 : -1)"
             if pdg[i] == 21:
                 em.w(f"const wf<T> x{i} = ext_vec<T>(q[{i}], {lam}, {'false' if incoming[i] else 'true'});")
+                self.fresh_fn[f"x{i}"] = "fresh_pol"
             elif i == q_leg:
                 em.w(f"const wf<T> x{i} = ext_bra<T>(q[{i}], mt, {lam}, false);")
             else:
                 em.w(f"const wf<T> x{i} = ext_ket<T>(q[{i}], mt, {lam}, true);")
             self.names[("X", i)] = f"x{i}"
-            self.fresh_fn[f"x{i}"] = ""
         self.inmask = sum(1 << i for i in range(n_ext) if incoming[i])
         self.counter = 0
 
     def fr(self, v: str) -> str:
-        fn = self.fresh_fn.get(v, "fresh")
-        return f"{fn}({v})" if fn else v
+        return f"{self.fresh_fn.get(v, 'fresh')}({v})"
 
     def mom(self, var: str, mask: int) -> str:
         return (f"double {var}d[4]; flow_momentum<{mask}u, {self.inmask}u, NEXT>({var}d, q); "

@@ -322,10 +322,9 @@ __device__ __forceinline__ float fresh(float x) {
   asm volatile("" : "+v"(x));
   return x;
 }
-// Internal currents get fresh copies only in double precision: there the
-// merged live ranges spill to scratch, while in single precision the saved
-// copies outweigh them (measured on gfx950: FP64 -2%, FP32 -15% time with
-// this split).  External wavefunctions are used as they are.
+// Wavefunctions get fresh copies only in double precision: there merged live
+// ranges spill to scratch memory (measured on gfx950), while in single
+// precision the registers suffice and the copies would only cost moves.
 template <typename T> __device__ __forceinline__ wf<T> fresh(const wf<T>& w) {
   if constexpr (sizeof(T) == 4) {
     return w;
@@ -333,6 +332,19 @@ template <typename T> __device__ __forceinline__ wf<T> fresh(const wf<T>& w) {
     wf<T> r = w;
     asm volatile("" : "+v"(r.c[0].re), "+v"(r.c[0].im), "+v"(r.c[1].re), "+v"(r.c[1].im), "+v"(r.c[2].re),
                  "+v"(r.c[2].im), "+v"(r.c[3].re), "+v"(r.c[3].im));
+    return r;
+  }
+}
+// External polarisation vectors have a vanishing time component and a real
+// z component; those constants stay visible to the compiler.
+template <typename T> __device__ __forceinline__ wf<T> fresh_pol(const wf<T>& w) {
+  if constexpr (sizeof(T) == 4) {
+    return w;
+  } else {
+    wf<T> r = w;
+    asm volatile("" : "+v"(r.c[1].re), "+v"(r.c[1].im), "+v"(r.c[2].re), "+v"(r.c[2].im), "+v"(r.c[3].re));
+    r.c[0] = mk<T>((T)0, (T)0);
+    r.c[3].im = (T)0;
     return r;
   }
 }

@@ -305,6 +305,7 @@ int mgme_process_info(const mgme_process* proc, mgme_info* out) {
   out->norm_factor = proc->norm_factor;
   out->flops_per_hel = e.flops_per_hel;
   out->flops_per_event = e.flops_per_event;
+  out->kernel_hash = e.kernel_hash;
   return MGME_OK;
 }
 

@@ -25,6 +25,7 @@ struct ProcEntry {
   int n_gluons;
   int staged;                   // colour-flow vector staged in device memory (many flows)
   int n_overflow;               // staged: overflow slots per (event, helicity)
+  unsigned long long kernel_hash;  // FNV-1a hash of the process's generated kernel sources
 };
 
 // Device workspace one mgme_matrix_element call takes from the stream-ordered
