@@ -38,7 +38,13 @@ FP32_VALU_PEAK_TFLOPS = 78.6   # the same lanes without packed FP32 instructions
 # kernel_hash; each counter is scaled by what it reads for a plain
 # device-to-device copy of known size (FETCH_SIZE reports half the bytes
 # read on this GPU, WRITE_SIZE all of them).
-TRAFFIC = {}
+# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE
+# (KiB per launch), each scaled by what the same counter reads for a plain
+# 1 GiB device copy; valid only for the kernels whose hash is recorded.
+TRAFFIC = {
+    ("gg_ttgg", 0): {"kernel_hash": 928121246631932704, "fetch_kib": 51787.6, "write_kib": 4096.0,
+                     "fetch_scale": 2.0, "write_scale": 1.0},
+}
 # The paper's standalone CUDA throughput on one V100 for this workload
 # (g g -> t t~ g g, double, grid 524288): 4.21E5 MEs/s.
 PAPER_MES = {("gg_ttgg", 0): 4.21e5, ("gg_ttgg", 1): 8.77e5}

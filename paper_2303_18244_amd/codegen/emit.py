@@ -83,7 +83,7 @@ class GGBody:
     helicity configuration: external wavefunctions, the currents each
     amplitude needs (computed at first use), and the amplitude values."""
 
-    def __init__(self, sched: Schedule, pdg: List[int], em: Emitter):
+    def __init__(self, sched: Schedule, pdg: List[int], em: Emitter, fresh_externals: bool = True):
         self.sched = sched
         self.em = em
         n_ext = len(pdg)
@@ -101,11 +101,14 @@ class GGBody:
             else:
                 em.w(f"const wf<T> x{i} = ext_ket<T>(q[{i}], mt, {lam}, true);")
             self.names[("X", i)] = f"x{i}"
+            if not fresh_externals:
+                self.fresh_fn[f"x{i}"] = ""
         self.inmask = sum(1 << i for i in range(n_ext) if incoming[i])
         self.counter = 0
 
     def fr(self, v: str) -> str:
-        return f"{self.fresh_fn.get(v, 'fresh')}({v})"
+        fn = self.fresh_fn.get(v, "fresh")
+        return f"{fn}({v})" if fn else v
 
     def mom(self, var: str, mask: int) -> str:
         return (f"double {var}d[4]; flow_momentum<{mask}u, {self.inmask}u, NEXT>({var}d, q); "
@@ -228,7 +231,10 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
     n_rmw = 0
     for chunk in chunks:
         em = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
-        body = GGBody(sched, pdg, em)
+        # External wavefunctions are used without fresh copies here: with them
+        # the double-precision chunk kernels spill far more and returned wrong
+        # results on gfx950 (cause not isolated); without them they pass parity.
+        body = GGBody(sched, pdg, em, fresh_externals=False)
         uses: Dict[int, List[int]] = {}
         for j, a in enumerate(chunk):
             for f, _, _ in a.coeffs:
