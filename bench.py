@@ -27,6 +27,7 @@ WORKLOADS = {
     # name: (pdg key, events per batch, sqrt(s) GeV)
     "gg_ttgg": ("gg_ttgg", 524288, 1500.0),
     "gg_ttggg": ("gg_ttggg", 65536, 1500.0),
+    "gg_ttg": ("gg_ttg", 65536, 1500.0),
     "gg_tt": ("gg_tt", 524288, 1500.0),
     "ee_mumu": ("ee_mumu", 16384, 500.0),
 }
@@ -38,11 +39,8 @@ FP32_VALU_PEAK_TFLOPS = 78.6   # the same lanes without packed FP32 instructions
 # kernel_hash; each counter is scaled by what it reads for a plain
 # device-to-device copy of known size (FETCH_SIZE reports half the bytes
 # read on this GPU, WRITE_SIZE all of them).
-# HBM traffic of the dominant kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE
-# (KiB per launch), each scaled by what the same counter reads for a plain
-# 1 GiB device copy; valid only for the kernels whose hash is recorded.
 TRAFFIC = {
-    ("gg_ttgg", 0): {"kernel_hash": 928121246631932704, "fetch_kib": 51787.6, "write_kib": 4096.0,
+    ("gg_ttgg", "fp64"): {"kernel_hash": 928121246631932704, "fetch_kib": 51787.6, "write_kib": 4096.0,
                      "fetch_scale": 2.0, "write_scale": 1.0},
 }
 # The paper's standalone CUDA throughput on one V100 for this workload
@@ -50,8 +48,10 @@ TRAFFIC = {
 PAPER_MES = {("gg_ttgg", 0): 4.21e5, ("gg_ttgg", 1): 8.77e5}
 
 
-def cpu_baseline(name: str, n_events: int, mom_host, seconds: float = 12.0):
-    """Oracle MEs/s on the host cores, on the leading events of the batch."""
+def cpu_baseline(name: str, n_events: int, mom_host, me_gpu=None, result=None, seconds: float = 12.0):
+    """Oracle MEs/s on the host cores, on the leading events of the batch.
+    The oracle's values on that sample also give the error of the GPU
+    result `me_gpu` (stored in result["vs_oracle"])."""
     import numpy as np
 
     import oracle
@@ -65,8 +65,13 @@ def cpu_baseline(name: str, n_events: int, mom_host, seconds: float = 12.0):
     per_event = (time.perf_counter() - t0) / len(probe)
     n = int(min(len(mom_host), max(len(probe), seconds / max(per_event, 1e-9))))
     t0 = time.perf_counter()
-    P.me(mom_host[:n], nthreads=threads)
+    ref = P.me(mom_host[:n], nthreads=threads)
     wall = time.perf_counter() - t0
+    if me_gpu is not None and result is not None:
+        rel = np.abs(me_gpu[:n] - ref) / np.abs(ref)
+        result["vs_oracle"] = {"events": n, "rel_err_median": float(np.median(rel)),
+                               "rel_err_p99": float(np.quantile(rel, 0.99)), "rel_err_max": float(rel.max()),
+                               "batch_mean_rel": float(abs(me_gpu[:n].sum() / ref.sum() - 1.0))}
     return {"value": n / wall, "unit": "MEs/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} of the {n_events} benchmark events, all helicities, FP64, "
                       f"{threads} threads, {wall:.1f} s wall"}
@@ -139,7 +144,7 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="gg_ttgg", choices=list(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "mixed"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "mixed", "fp64_fp32colour"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="instead of the benchmark, run the serving mix with N requests")
@@ -178,7 +183,7 @@ def main(argv=None) -> int:
     import paper_2303_18244_amd as M
 
     key, nevt, sqrt_s = WORKLOADS[a.workload]
-    prec = {"fp64": M.FP64, "fp32": M.FP32, "mixed": M.MIXED}[a.precision]
+    prec = {"fp64": M.FP64, "fp32": M.FP32, "mixed": M.MIXED, "fp64_fp32colour": M.FP64_FP32COLOUR}[a.precision]
     P = M.Process(M.PROCESSES[key])
     info = P.info
     dev = torch.device("cuda", 0)
@@ -210,7 +215,7 @@ def main(argv=None) -> int:
     ngood = info["n_good_hel"]
     flops = (info["flops_per_hel"] * ngood + info["flops_per_event"]) * nevt
     achieved = flops / (me_ms * 1e-3) * 1e-12
-    peak = FP64_VALU_PEAK_TFLOPS if prec == M.FP64 else FP32_VALU_PEAK_TFLOPS
+    peak = FP64_VALU_PEAK_TFLOPS if prec in (M.FP64, M.FP64_FP32COLOUR) else FP32_VALU_PEAK_TFLOPS
     tr = TRAFFIC.get((key, a.precision))
     traffic = None
     if tr is not None and tr["kernel_hash"] == info["kernel_hash"]:
@@ -228,7 +233,7 @@ def main(argv=None) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": (value / PAPER_MES[(key, prec)]) if (key, prec) in PAPER_MES else None,
-        "dtype": {M.FP64: "f64", M.FP32: "f32", M.MIXED: "f32+f16"}[prec],
+        "dtype": {M.FP64: "f64", M.FP32: "f32", M.MIXED: "f32+f16", M.FP64_FP32COLOUR: "f64+f32"}[prec],
         "data": "synthetic (RAMBO flat phase space, Philox seed 230318244)",
         "config": {"workload": key, "events_per_batch": nevt, "sqrt_s_gev": sqrt_s,
                    "precision": a.precision, "good_helicities": ngood, "diagrams": info["n_diagrams"],
@@ -239,10 +244,31 @@ def main(argv=None) -> int:
                      "kernel": f"me_kernel<{'double' if prec == M.FP64 else 'float'}> ({key}, {a.precision})",
                      "flops_per_launch": flops},
     }
+    if info["n_colour"] > 24 or prec != M.FP64:
+        result["roofline"]["kernel"] = (f"every kernel of one mgme_matrix_element call ({key}, {a.precision}): "
+                                        "diagram kernels, colour sum and helicity sum, timed together")
+    if prec != M.FP64:
+        # accuracy and speed against plain FP64 on the same GPU and the same events
+        me64 = torch.empty_like(me)
+        P.matrix_element(mom, precision=M.FP64, out=me64)
+        torch.cuda.synchronize()
+        e64 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+        for e0, e1 in e64:
+            e0.record(stream)
+            P.matrix_element(mom, precision=M.FP64, out=me64)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = sum(e0.elapsed_time(e1) for e0, e1 in e64) / len(e64)
+        rel = ((me - me64).abs() / me64.abs()).cpu().numpy()
+        result["vs_fp64_same_gpu"] = {
+            "fp64_me_ms_per_launch": ms64, "speedup_me_only": ms64 / me_ms,
+            "rel_err_median": float(np.median(rel)), "rel_err_p99": float(np.quantile(rel, 0.99)),
+            "rel_err_max": float(rel.max()),
+            "batch_mean_rel": float(abs(me.sum().item() / me64.sum().item() - 1.0)), "events": nevt}
     if not a.no_cpu_baseline:
         host = mom.cpu().numpy().transpose(2, 0, 1)
         host = np.ascontiguousarray(host[:65536])
-        result["cpu_baseline"] = cpu_baseline(key, nevt, host)
+        result["cpu_baseline"] = cpu_baseline(key, nevt, host, me.cpu().numpy(), result)
     print(json.dumps(result), flush=True)
     return 0
 

@@ -46,8 +46,11 @@ typedef enum {
   MGME_FP64 = 0, /* plain method: every step in double precision */
   MGME_FP32 = 1, /* diagrams in single precision; momenta, propagator denominators,
                     colour quadratic form and helicity sum in double */
-  MGME_MIXED = 2 /* single-precision diagrams; colour sum on the matrix cores with J split into two
-                    power-of-two-scaled half-precision parts (FP32 accumulation); helicity sum in double */
+  MGME_MIXED = 2, /* single-precision diagrams; colour sum on the matrix cores with J split into two
+                     power-of-two-scaled half-precision parts (FP32 accumulation); helicity sum in double */
+  MGME_FP64_FP32COLOUR = 3 /* the "mixed" mode of the paper (section 3, Table 3): diagrams and J in
+                              double, colour algebra Re(J^dagger C J) in single precision, helicity sum
+                              in double */
 } mgme_precision;
 
 /* Couplings and masses.  alpha_s is fixed (no running).  The top width wt

@@ -17,7 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["oracle.cpp", "oracle.h", "process.hpp", "lorentz.hpp", "colour.hpp", "philox_rambo.hpp"]
+_SOURCES = ["oracle.cpp", "oracle.h", "process.hpp", "lorentz.hpp", "colour.hpp", "philox_rambo.hpp", "events.hpp"]
 
 
 def build(force: bool = True) -> str:
@@ -64,6 +64,11 @@ def lib():
                                 ctypes.c_int, dp]
         L.oracle_me_hel.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
         L.oracle_gauge.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
+        L.oracle_event_weights.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, dp, dp]
+        L.oracle_unweight.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]
+        L.oracle_unweight.restype = ctypes.c_int64
+        L.oracle_select.argtypes = [ctypes.c_void_p, dp, ctypes.c_double, ctypes.c_double,
+                                    ctypes.POINTER(ctypes.c_int), dp]
         _lib = L
     return _lib
 
@@ -109,6 +114,26 @@ def rambo(masses_out, sqrt_s: float, seed: int, first_event: int, nevt: int):
     if rc != 0:
         raise ValueError("oracle_rambo failed")
     return mom, wgt
+
+
+def event_weights(wgt, me, sqrt_s: float):
+    """Cross-section weights in pb and (sum w, sum w^2, max w)."""
+    wgt = np.ascontiguousarray(wgt, dtype=np.float64)
+    me = np.ascontiguousarray(me, dtype=np.float64)
+    w = np.zeros(len(wgt))
+    st = np.zeros(3)
+    if lib().oracle_event_weights(len(wgt), _dp(wgt), _dp(me), sqrt_s, _dp(w), _dp(st)) != 0:
+        raise ValueError("oracle_event_weights failed")
+    return w, st
+
+
+def unweight(w, r, w_ref: float) -> np.ndarray:
+    """Indices of the events kept by hit-or-miss against w_ref."""
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    idx = np.zeros(max(1, len(w)), dtype=np.int64)
+    k = lib().oracle_unweight(len(w), _dp(w), _dp(r), w_ref, idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return idx[:k].copy()
 
 
 def external(kind: str, p, mass: float, hel: int) -> np.ndarray:
@@ -171,6 +196,14 @@ class Process:
         out = np.zeros(self.n_hel)
         lib().oracle_me_hel(self._h, _dp(mom1), precision, _dp(out))
         return out
+
+    def select(self, mom1: np.ndarray, r_hel: float, r_col: float):
+        """(helicity code, colour flow, margins) for one event."""
+        mom1 = np.ascontiguousarray(mom1, dtype=np.float64)
+        out = (ctypes.c_int * 2)()
+        margin = np.zeros(2)
+        lib().oracle_select(self._h, _dp(mom1), r_hel, r_col, out, _dp(margin))
+        return int(out[0]), int(out[1]), margin
 
     def gauge(self, mom1: np.ndarray, leg: int):
         mom1 = np.ascontiguousarray(mom1, dtype=np.float64)

@@ -7,6 +7,7 @@
 #include <thread>
 #include <vector>
 
+#include "events.hpp"
 #include "lorentz.hpp"
 #include "philox_rambo.hpp"
 #include "process.hpp"
@@ -151,6 +152,35 @@ int oracle_gauge(void* proc, const double* mom, int leg, double out[2]) {
   }
   out[0] = mx_rep;
   out[1] = mx;
+  return 0;
+}
+
+int oracle_event_weights(int64_t nevt, const double* wgt, const double* me, double sqrt_s, double* w,
+                         double stats[3]) {
+  if (nevt < 0 || !(sqrt_s > 0)) return -1;
+  oracle::event_weights(nevt, wgt, me, sqrt_s, w);
+  oracle::weight_stats(nevt, w, stats);
+  return 0;
+}
+
+int64_t oracle_unweight(int64_t nevt, const double* w, const double* r, double w_ref, int64_t* idx) {
+  if (nevt < 0) return -1;
+  return oracle::unweight(nevt, w, r, w_ref, idx);
+}
+
+int oracle_select(void* proc, const double* mom, double r_hel, double r_col, int out[2], double margin[2]) {
+  auto* P = static_cast<oracle::Process*>(proc);
+  const auto ev = P->make_event<double>(mom);
+  std::vector<std::complex<double>> amp, J;
+  std::vector<double> me_h(P->n_hel), jamp2(P->ncol, 0.0);
+  for (int h = 0; h < P->n_hel; ++h) {
+    P->term_amplitudes(ev, h, -1, amp);
+    P->flows(amp, J);
+    me_h[h] = P->colour_sum(J) * P->norm;
+    for (int s = 0; s < P->ncol; ++s) jamp2[s] += std::norm(J[s]);
+  }
+  out[0] = oracle::choose(me_h, r_hel, &margin[0]);
+  out[1] = oracle::choose(jamp2, r_col, &margin[1]);
   return 0;
 }
 

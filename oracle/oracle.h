@@ -55,6 +55,20 @@ int oracle_me_hel(void* proc, const double* mom, int precision, double* me_hel);
  * out[1] = the same maximum without it. */
 int oracle_gauge(void* proc, const double* mom, int leg, double out[2]);
 
+/* Cross-section weights w[e] = (wgt[e] * me[e]) * (0.3893793721e9 / (2 s)) in
+ * pb for massless colliding partons, and stats = (sum w, sum w^2, max w). */
+int oracle_event_weights(int64_t nevt, const double* wgt, const double* me, double sqrt_s, double* w,
+                         double stats[3]);
+/* Hit-or-miss unweighting: indices e with r[e] * w_ref < w[e], increasing;
+ * returns their number. */
+int64_t oracle_unweight(int64_t nevt, const double* w, const double* r, double w_ref, int64_t* idx);
+/* Helicity and leading-colour choice for one event: out[0] = helicity code
+ * (chosen with probability |M_h|^2 / |M|^2, helicities in code order),
+ * out[1] = colour flow in basis order (probability proportional to
+ * sum_h |J_s(h)|^2); margin[i] = distance of the threshold to the nearest
+ * running sum, relative to the total. */
+int oracle_select(void* proc, const double* mom, double r_hel, double r_col, int out[2], double margin[2]);
+
 #ifdef __cplusplus
 }
 #endif

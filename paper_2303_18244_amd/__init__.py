@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmgme.so")
 
 MGME_OK, MGME_EINVAL, MGME_EUNSUPPORTED, MGME_ENOMEM, MGME_EDEVICE = 0, -1, -2, -3, -4
-FP64, FP32, MIXED = 0, 1, 2
+FP64, FP32, MIXED, FP64_FP32COLOUR = 0, 1, 2, 3
 
 PROCESSES = {
     "ee_mumu": [-11, 11, -13, 13],

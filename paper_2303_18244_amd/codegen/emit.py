@@ -61,20 +61,21 @@ class Emitter:
 
 
 def colour_sum_lines(C: List[List[Fraction]], den: int) -> List[str]:
-    """Lines computing me += Re(J^dagger C J) * den (integer numerators)."""
+    """Lines computing mc += Re(J^dagger C J) * den (integer numerators) in
+    the colour precision TC of the kernel."""
     n = len(C)
     out = []
     for s in range(n):
-        parts_r = [f"{float(C[s][s] * den)!r} * (double)J[{s}].re"]
-        parts_i = [f"{float(C[s][s] * den)!r} * (double)J[{s}].im"]
+        parts_r = [f"(TC){float(C[s][s] * den)!r} * (TC)J[{s}].re"]
+        parts_i = [f"(TC){float(C[s][s] * den)!r} * (TC)J[{s}].im"]
         for t in range(s + 1, n):
             v = C[s][t] * den * 2
             if v == 0:
                 continue
-            parts_r.append(f"{float(v)!r} * (double)J[{t}].re")
-            parts_i.append(f"{float(v)!r} * (double)J[{t}].im")
-        out.append(f"me += (double)J[{s}].re * ({' + '.join(parts_r)}) + "
-                   f"(double)J[{s}].im * ({' + '.join(parts_i)});")
+            parts_r.append(f"(TC){float(v)!r} * (TC)J[{t}].re")
+            parts_i.append(f"(TC){float(v)!r} * (TC)J[{t}].im")
+        out.append(f"mc += (TC)J[{s}].re * ({' + '.join(parts_r)}) + "
+                   f"(TC)J[{s}].im * ({' + '.join(parts_i)});")
     return out
 
 
@@ -199,7 +200,8 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
         body.amplitude(a)
         upd = " ".join(f"acc(J[{f}], a, {re}, {im});" for f, re, im in a.coeffs)
         em.w(f"  {upd} }}")
-    colour = ["      double me = 0.0;"] + ["  " + ln for ln in colour_sum_lines(C, cden)]
+    colour = (["      TC mc = (TC)0;"] + ["  " + ln for ln in colour_sum_lines(C, cden)]
+              + ["      const double me = (double)mc;"])
     flops_hel = sched.flops_per_helicity() + 2 * ncol * ncol + 4 * ncol + 90 * n_ext
     return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "\n".join(em.lines),
                     colour="\n".join(colour))
@@ -335,7 +337,7 @@ def emit_ee_process(name: str, pdg: List[int]) -> Dict:
     meta = dict(name=name, pdg=pdg, n_ext=4, n_diagrams=2, n_terms=2, ncol=1, cden=1, n_currents=4,
                 n_amps=2, gs_power=0, spin_colour_avg=4, ident=1, kind="ee",
                 flops_per_hel=2 * 128 + 2 * 30 + 20, flops_per_event=40, body="\n".join(lines),
-                colour="      double me = (double)J[0].re * (double)J[0].re + (double)J[0].im * (double)J[0].im;")
+                colour="      const double me = (double)((TC)J[0].re * (TC)J[0].re + (TC)J[0].im * (TC)J[0].im);")
     return meta
 
 
@@ -352,11 +354,12 @@ namespace {name} {{
 constexpr int NEXT = {n_ext};
 constexpr int NCOL = {ncol};
 
+// T: precision of the diagrams; TC: precision of the colour quadratic form.
 // MODE 0: |M|^2 summed over the good helicities into out[e];
 // MODE 1: each helicity's contribution into out[ih*ldo + e];
 // MODE 2: the colour-flow vector J of every helicity into
 //         Jout[(ih*NCOL + s)*ldo + e] (single precision) for the matrix-core colour sum.
-template <typename T, int MODE>
+template <typename T, int MODE, typename TC = double>
 __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restrict__ mom, long long nevt,
                                                           long long ld, const MeArgs args,
                                                           double* __restrict__ out, long long ldo,
@@ -434,6 +437,10 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
   if (prec == 0) {{
     if (per_hel) me_kernel<double, 1><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
     else me_kernel<double, 0><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
+  }} else if (prec == 3) {{
+    // double-precision diagrams, single-precision colour algebra
+    if (per_hel) me_kernel<double, 1, float><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
+    else me_kernel<double, 0, float><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
   }} else {{
     if (per_hel) me_kernel<float, 1><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
     else me_kernel<float, 0><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
@@ -520,7 +527,7 @@ __constant__ double kC[NCOL * NCOL] = {{{cnum}}};
 // Adds the overflow slots to J (fixed at generation), then
 // me_h = sum_st C_st Re(conj(J_s) J_t) with blocks of NB flows of C J held in
 // registers while J streams from memory.
-template <typename T>
+template <typename T, typename TC>
 __global__ void __launch_bounds__(256) colour_kernel(long long nevt, const MeArgs args, cx<T>* __restrict__ Jbuf,
                                                     const cx<T>* __restrict__ Ovbuf, long long ldp,
                                                     double* __restrict__ out, long long ldo, double scale) {{
@@ -531,17 +538,17 @@ __global__ void __launch_bounds__(256) colour_kernel(long long nevt, const MeArg
   const cx<T>* __restrict__ Ov = Ovbuf + (long long)hs * NOV * ldp + e;
   (void)Ov;
 {overflow_sums}
-  double me = 0.0;
+  TC me = (TC)0;
   for (int b = 0; b < NCOL; b += NB) {{
-    double yr[NB], yi[NB];
+    TC yr[NB], yi[NB];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) yr[k] = yi[k] = 0.0;
+    for (int k = 0; k < NB; ++k) yr[k] = yi[k] = (TC)0;
     for (int t = 0; t < NCOL; ++t) {{
       const cx<T> jt = J[(long long)t * ldp];
-      const double jr = (double)jt.re, ji = (double)jt.im;
+      const TC jr = (TC)jt.re, ji = (TC)jt.im;
 #pragma unroll
       for (int k = 0; k < NB; ++k) {{
-        const double c = kC[(b + k) * NCOL + t];
+        const TC c = (TC)kC[(b + k) * NCOL + t];
         yr[k] += c * jr;
         yi[k] += c * ji;
       }}
@@ -549,10 +556,10 @@ __global__ void __launch_bounds__(256) colour_kernel(long long nevt, const MeArg
 #pragma unroll
     for (int k = 0; k < NB; ++k) {{
       const cx<T> js = J[(long long)(b + k) * ldp];
-      me += (double)js.re * yr[k] + (double)js.im * yi[k];
+      me += (TC)js.re * yr[k] + (TC)js.im * yi[k];
     }}
   }}
-  out[(long long)hs * ldo + e] = me * scale;
+  out[(long long)hs * ldo + e] = (double)me * scale;
 }}
 
 // Adds the overflow slots into J (mixed precision: before the matrix-core colour sum).
@@ -580,7 +587,7 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
                                           hipStream_t stream) {{
   using namespace mgme::{name};
   const int nh = args->nhel;
-  const int dprec = prec == 0 ? 0 : 1;  // diagram precision
+  const int dprec = (prec == 0 || prec == 3) ? 0 : 1;  // diagram precision
   const size_t tsize = dprec == 0 ? sizeof(mgme::cx<double>) : sizeof(mgme::cx<float>);
   const size_t per_event = (size_t)nh * ((NCOL + NOV) * tsize + sizeof(double));
   const size_t budget = (size_t){workspace_bytes};
@@ -605,11 +612,14 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
     const long long ldd = per_hel ? ldo : sub;
     const double sc = per_hel ? factor : 1.0;
     if (prec == 0) {{
-      colour_kernel<double><<<grid, 256, 0, stream>>>(n, *args, (mgme::cx<double>*)Jbuf,
-                                                     (const mgme::cx<double>*)Ovbuf, sub, dst, ldd, sc);
+      colour_kernel<double, double><<<grid, 256, 0, stream>>>(n, *args, (mgme::cx<double>*)Jbuf,
+                                                             (const mgme::cx<double>*)Ovbuf, sub, dst, ldd, sc);
+    }} else if (prec == 3) {{
+      colour_kernel<double, float><<<grid, 256, 0, stream>>>(n, *args, (mgme::cx<double>*)Jbuf,
+                                                            (const mgme::cx<double>*)Ovbuf, sub, dst, ldd, sc);
     }} else if (prec == 1) {{
-      colour_kernel<float><<<grid, 256, 0, stream>>>(n, *args, (mgme::cx<float>*)Jbuf,
-                                                    (const mgme::cx<float>*)Ovbuf, sub, dst, ldd, sc);
+      colour_kernel<float, double><<<grid, 256, 0, stream>>>(n, *args, (mgme::cx<float>*)Jbuf,
+                                                            (const mgme::cx<float>*)Ovbuf, sub, dst, ldd, sc);
     }} else {{
       fold_kernel<float><<<grid, 256, 0, stream>>>(n, *args, (mgme::cx<float>*)Jbuf,
                                                   (const mgme::cx<float>*)Ovbuf, sub);

@@ -26,7 +26,8 @@ struct MeArgs {
   int hel[MGME_MAX_HEL];    // helicity codes: bit (n_ext-1-leg) set for helicity +1
 };
 
-// prec: 0 FP64, 1 FP32 diagrams, 2 FP32 diagrams + 16-bit matrix-core colour sum.
+// prec: 0 FP64, 1 FP32 diagrams, 2 FP32 diagrams + 16-bit matrix-core colour sum,
+// 3 FP64 diagrams + FP32 colour algebra.
 using LaunchFn = hipError_t (*)(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                 const MeArgs* args, double* out, long long ldo, hipStream_t stream);
 

@@ -32,6 +32,10 @@ namespace {
 
 thread_local std::string g_error;
 
+bool valid_precision(int p) {
+  return p == MGME_FP64 || p == MGME_FP32 || p == MGME_MIXED || p == MGME_FP64_FP32COLOUR;
+}
+
 int fail(int code, const std::string& msg) {
   g_error = msg;
   return code;
@@ -164,7 +168,7 @@ long long workspace_bytes(const ProcEntry& e, int nhel, long long nevt, int prec
   if (nevt <= 0) return 0;
   const long long round64 = (nevt + 63) / 64 * 64;
   if (e.staged) {
-    const long long tsize = prec == 0 ? 16 : 8;
+    const long long tsize = (prec == MGME_FP64 || prec == MGME_FP64_FP32COLOUR) ? 16 : 8;
     const long long per_event = (long long)nhel * ((e.n_colour + e.n_overflow) * tsize + 8);
     long long sub = (12ll << 30) / per_event / 64 * 64;
     if (sub < 64) sub = 64;
@@ -188,7 +192,7 @@ extern "C" {
 
 int mgme_workspace_bytes(const mgme_process* proc, long long nevt, int precision, long long* bytes) {
   if (!proc || !bytes || nevt < 0) return fail(MGME_EINVAL, "bad argument");
-  if (precision < MGME_FP64 || precision > MGME_MIXED) return fail(MGME_EINVAL, "unknown precision");
+  if (!valid_precision(precision)) return fail(MGME_EINVAL, "unknown precision");
   *bytes = mgme::workspace_bytes(*proc->entry, proc->args.nhel, nevt, precision);
   return MGME_OK;
 }
@@ -341,8 +345,7 @@ int mgme_matrix_element(const mgme_process* proc, const double* d_mom, long long
                         double* d_me, void* hip_stream) {
   int rc = check_batch(proc, d_mom, d_me, nevt, ld);
   if (rc != MGME_OK) return rc;
-  if (precision != MGME_FP64 && precision != MGME_FP32 && precision != MGME_MIXED)
-    return fail(MGME_EINVAL, "unknown precision");
+  if (!valid_precision(precision)) return fail(MGME_EINVAL, "unknown precision");
   if ((rc = check_pending("mgme_matrix_element")) != MGME_OK) return rc;
   if (nevt == 0) return MGME_OK;
   if ((rc = select_device(proc->device)) != MGME_OK) return rc;
@@ -357,8 +360,7 @@ int mgme_matrix_element_per_helicity(const mgme_process* proc, const double* d_m
   int rc = check_batch(proc, d_mom, d_out, nevt, ld);
   if (rc != MGME_OK) return rc;
   if (ldo < nevt) return fail(MGME_EINVAL, "ldo < nevt");
-  if (precision != MGME_FP64 && precision != MGME_FP32 && precision != MGME_MIXED)
-    return fail(MGME_EINVAL, "unknown precision");
+  if (!valid_precision(precision)) return fail(MGME_EINVAL, "unknown precision");
   if ((rc = check_pending("mgme_matrix_element_per_helicity")) != MGME_OK) return rc;
   if (nevt == 0) return MGME_OK;
   if ((rc = select_device(proc->device)) != MGME_OK) return rc;

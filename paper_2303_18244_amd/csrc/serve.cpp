@@ -256,7 +256,7 @@ int mgme_server_submit(mgme_server* s, const mgme_process* proc, const double* d
   if (!s || !id || (!proc && !s->cfg.fake_executor)) return sfail(MGME_EINVAL, "NULL argument");
   if (nevt < 1 || ld < nevt || (!s->cfg.fake_executor && (!d_mom || !d_me)))
     return sfail(MGME_EINVAL, "bad batch");
-  if (precision < MGME_FP64 || precision > MGME_MIXED) return sfail(MGME_EINVAL, "unknown precision");
+  if (precision < MGME_FP64 || precision > MGME_FP64_FP32COLOUR) return sfail(MGME_EINVAL, "unknown precision");
   long long ws = 0;
   if (s->cfg.fake_executor) ws = (long long)s->cfg.fake_bytes_per_event * nevt;
   else if (mgme_workspace_bytes(proc, nevt, precision, &ws) != MGME_OK) return sfail(MGME_EINVAL, "bad process");

@@ -145,6 +145,28 @@ def test_mixed_accuracy(lib_procs, oracle_procs, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
+def test_fp64_diagrams_fp32_colour_accuracy(lib_procs, oracle_procs, name):
+    """The paper's mixed mode: double-precision diagrams, single-precision
+    colour algebra (section 3).  Same criterion as the other reduced-precision
+    modes; the error comes from the colour quadratic form alone, so it is also
+    bounded per event by the float rounding of that form."""
+    torch = _torch()
+    import paper_2303_18244_amd as M
+
+    P = _proc(lib_procs, name)
+    n, _, sq = CASES[name]
+    mom, _ = P.rambo(sq, SEED, 0, n)
+    me = P.matrix_element(mom, precision=M.FP64_FP32COLOUR).cpu().numpy()
+    ref = oracle_procs[name].me(_host(mom, n), nthreads=NTHREADS)
+    rel = np.abs(me / ref - 1.0)
+    mean_rel = abs(me.mean() / ref.mean() - 1.0)
+    print(f"{name} FP64 diagrams + FP32 colour vs oracle on {n} events: batch-mean {mean_rel:.2e}, "
+          f"median {np.median(rel):.2e}, p99 {np.quantile(rel, 0.99):.2e}, max {rel.max():.2e}")
+    assert mean_rel <= 1e-5
+    assert np.median(rel) <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(CASES))
 def test_full_size_sampled(lib_procs, oracle_procs, name):
     """The configuration's full batch in one launch: sampled events against the
     oracle, and the leading events bitwise equal to a small batch (no
@@ -248,7 +270,7 @@ def test_determinism_and_ragged_edges(lib_procs):
 
 
 @pytest.mark.parametrize("name", ["gg_ttgg", "gg_ttggg"])
-@pytest.mark.parametrize("prec", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_staging_edges(lib_procs, name, prec):
     """Ragged batch sizes, a padded leading dimension and batches spanning
     several sub-batches of the staging buffers give the same per-event values
