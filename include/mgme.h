@@ -140,6 +140,60 @@ int mgme_workspace_bytes(const mgme_process* proc, long long nevt, int precision
 int mgme_matrix_element_per_helicity(const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
                                      int precision, double* d_out, long long ldo, void* hip_stream);
 
+/* |M|^2 as mgme_matrix_element, and for each event a helicity configuration
+ * and a leading colour flow drawn at random, as an event generator writes
+ * them with an unweighted event (section 5 of the paper names this choice as
+ * the last feature added to its GPU workflow; the definitions here are ours):
+ *  - d_hel[e]: the helicity code (bit n_ext-1-leg set for helicity +1) of the
+ *    first good helicity, in increasing code order, whose running sum of
+ *    |M_h|^2 exceeds d_r_hel[e] times |M|^2;
+ *  - d_col[e]: the first colour flow s, in the order of mgme_colour_matrix's
+ *    basis (orderings of the gluon legs, lexicographic), whose running sum of
+ *    sum_h |J_s(h)|^2 exceeds d_r_col[e] times the total (J_s: the
+ *    colour-ordered amplitude of flow s; every flow of the trace basis is a
+ *    leading-colour flow);
+ *  - when no running sum exceeds the threshold (r within rounding of 1), the
+ *    last entry with a non-zero weight is taken.
+ * d_r_hel and d_r_col hold nevt uniform numbers in (0,1) (caller's random
+ * stream); d_me, d_hel, d_col receive nevt values.  The decisions are taken
+ * in double precision from the values of the chosen `precision`.  The call
+ * takes (n_good_hel + n_colour) * 8 bytes per event of extra workspace from
+ * the stream-ordered allocator (at most 4 GB, by sub-batches), plus the
+ * staging of mgme_matrix_element for staged processes and MGME_MIXED.
+ * Errors as mgme_matrix_element. */
+int mgme_select(const mgme_process* proc, const double* d_mom, long long nevt, long long ld, int precision,
+                const double* d_r_hel, const double* d_r_col, double* d_me, int* d_hel, int* d_col,
+                void* hip_stream);
+
+/* Cross-section weights of a batch of massless colliding partons at fixed
+ * sqrt_s (section 2 of the paper counts the cross-section calculation among
+ * the event generator's serial tasks):
+ *   d_w[e] = (d_wgt[e] * d_me[e]) * (0.3893793721e9 / (2 sqrt_s^2))   [pb]
+ * with d_wgt the phase-space weights of mgme_rambo (the flux is 2 s and
+ * (hbar c)^2 = 0.3893793721 GeV^2 mb converts GeV^-2 to pb; the constant is
+ * formed first, on the host).  d_stats[0..2] = (sum w, sum w^2, max w), so
+ * that sigma = sum w / N with error sqrt((sum w^2 / N - sigma^2) / (N - 1)).
+ * The sums use a fixed reduction order for a given nevt (the same inputs give
+ * the same bits).  d_w may be NULL (sums only); d_stats is 3 device doubles.
+ * Runs on the calling thread's current device, enqueued on hip_stream; takes
+ * at most 24 KB of workspace from the stream-ordered allocator.
+ * Errors: EINVAL (nevt < 0, NULL pointers, sqrt_s not positive), EDEVICE. */
+int mgme_event_weights(double sqrt_s, const double* d_wgt, const double* d_me, long long nevt, double* d_w,
+                       double* d_stats, void* hip_stream);
+
+/* Hit-or-miss unweighting (section 2 of the paper lists it among the serial
+ * tasks worth moving to the GPU): event e is kept when
+ * d_r[e] * (*d_w_ref) < d_w[e] (strictly), with d_r uniform in (0,1) and
+ * *d_w_ref (one device double, for example d_stats + 2 of
+ * mgme_event_weights, or a maximum from an earlier run) at least the largest
+ * weight.  d_idx (room for nevt) receives the kept event indices in
+ * increasing order and *d_nkept (one device long long) their number; each
+ * kept event then carries the weight *d_w_ref.  Runs on the current device;
+ * takes 16 bytes per 2048 events of workspace from the stream-ordered
+ * allocator.  Errors: EINVAL (nevt < 0, NULL pointers), EDEVICE. */
+int mgme_unweight(const double* d_w, const double* d_r, long long nevt, const double* d_w_ref, long long* d_idx,
+                  long long* d_nkept, void* hip_stream);
+
 const char* mgme_last_error(void);
 
 /* ------------------------------------------------------------------ serving

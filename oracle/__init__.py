@@ -40,10 +40,17 @@ class _Params(ctypes.Structure):
 _lib = None
 
 
+def _stale() -> bool:
+    if not os.path.exists(_LIB_PATH):
+        return True
+    t = os.path.getmtime(_LIB_PATH)
+    return any(os.path.getmtime(os.path.join(_HERE, f)) > t for f in _SOURCES)
+
+
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+        if _stale():
             build()
         L = ctypes.CDLL(_LIB_PATH)
         dp = ctypes.POINTER(ctypes.c_double)

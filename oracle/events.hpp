@@ -27,16 +27,18 @@ inline void event_weights(int64_t n, const double* wgt, const double* me, double
   for (int64_t e = 0; e < n; ++e) w[e] = (wgt[e] * me[e]) * k;
 }
 
-// sum w, sum w^2 and max w, in event order.
+// sum w, sum w^2 and max w, in event order; the sums accumulate in long
+// double, so their own rounding stays below n 2^-64 relative.
 inline void weight_stats(int64_t n, const double* w, double out[3]) {
-  double s = 0, s2 = 0, mx = 0;
+  long double s = 0, s2 = 0;
+  double mx = 0;
   for (int64_t e = 0; e < n; ++e) {
     s += w[e];
-    s2 += w[e] * w[e];
+    s2 += (long double)w[e] * w[e];
     if (w[e] > mx) mx = w[e];
   }
-  out[0] = s;
-  out[1] = s2;
+  out[0] = (double)s;
+  out[1] = (double)s2;
   out[2] = mx;
 }
 

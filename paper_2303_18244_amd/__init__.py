@@ -31,7 +31,8 @@ DEFAULT_PARAMS = dict(alpha_s=0.118, alpha_em=1.0 / 132.5, sin2w=0.2222, mz=91.1
 # Entry points declared in include/mgme.h.
 EXPORTS = ["mgme_process_create", "mgme_process_destroy", "mgme_process_info", "mgme_good_helicities",
            "mgme_colour_matrix", "mgme_rambo", "mgme_matrix_element", "mgme_matrix_element_per_helicity",
-           "mgme_workspace_bytes", "mgme_last_error", "mgme_server_create", "mgme_server_submit",
+           "mgme_workspace_bytes", "mgme_select", "mgme_event_weights", "mgme_unweight",
+           "mgme_last_error", "mgme_server_create", "mgme_server_submit",
            "mgme_server_wait", "mgme_server_drain", "mgme_server_get_stats", "mgme_server_destroy",
            "mgme_server_last_error"]
 
@@ -96,6 +97,9 @@ def lib() -> ctypes.CDLL:
         L.mgme_matrix_element.argtypes = [vp, dp, i64, i64, ctypes.c_int, dp, vp]
         L.mgme_matrix_element_per_helicity.argtypes = [vp, dp, i64, i64, ctypes.c_int, dp, i64, vp]
         L.mgme_workspace_bytes.argtypes = [vp, i64, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
+        L.mgme_select.argtypes = [vp, dp, i64, i64, ctypes.c_int, dp, dp, dp, vp, vp, vp]
+        L.mgme_event_weights.argtypes = [ctypes.c_double, dp, dp, i64, dp, dp, vp]
+        L.mgme_unweight.argtypes = [dp, dp, i64, dp, vp, vp, vp]
         L.mgme_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.c_int, ctypes.POINTER(vp)]
         L.mgme_server_submit.argtypes = [vp, vp, dp, i64, i64, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_ulonglong)]
         L.mgme_server_wait.argtypes = [vp, ctypes.c_ulonglong, ctypes.POINTER(ctypes.c_double)]
@@ -209,6 +213,62 @@ class Process:
                                                       int(precision), out.data_ptr(), int(out.shape[1]),
                                                       _stream_handle(stream)))
         return out[:, :nevt]
+
+    def select(self, mom, r_hel, r_col, nevt: Optional[int] = None, precision: int = FP64, stream=None):
+        """|M|^2 and a random helicity code and colour flow per event, from the
+        uniform numbers r_hel, r_col (float64 device tensors of nevt):
+        returns (me [nevt] float64, hel [nevt] int32, col [nevt] int32)."""
+        import torch
+        ld = mom.shape[-1]
+        nevt = ld if nevt is None else nevt
+        if mom.dtype != torch.float64 or not mom.is_contiguous() or mom.shape[:2] != (self.n_ext, 4):
+            raise MgmeError(MGME_EINVAL, "momenta must be a contiguous float64 tensor [n_ext, 4, ld]")
+        for r in (r_hel, r_col):
+            if r.dtype != torch.float64 or not r.is_contiguous() or r.numel() < nevt:
+                raise MgmeError(MGME_EINVAL, "random numbers must be contiguous float64 tensors of nevt")
+        n1 = max(nevt, 1)
+        me = torch.empty(n1, dtype=torch.float64, device=mom.device)
+        hel = torch.empty(n1, dtype=torch.int32, device=mom.device)
+        col = torch.empty(n1, dtype=torch.int32, device=mom.device)
+        _check(lib().mgme_select(self._h, mom.data_ptr(), int(nevt), int(ld), int(precision), r_hel.data_ptr(),
+                                 r_col.data_ptr(), me.data_ptr(), hel.data_ptr(), col.data_ptr(),
+                                 _stream_handle(stream)))
+        return me[:nevt], hel[:nevt], col[:nevt]
+
+
+def event_weights(sqrt_s: float, wgt, me, nevt: Optional[int] = None, want_weights: bool = True, stream=None):
+    """Cross-section weights in pb and (sum w, sum w^2, max w) as a device
+    tensor of 3 doubles; see mgme_event_weights."""
+    import torch
+    nevt = me.shape[0] if nevt is None else nevt
+    for t in (wgt, me):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < nevt:
+            raise MgmeError(MGME_EINVAL, "weights and matrix elements must be contiguous float64 tensors")
+    w = torch.empty(max(nevt, 1), dtype=torch.float64, device=me.device) if want_weights else None
+    stats = torch.empty(3, dtype=torch.float64, device=me.device)
+    _check(lib().mgme_event_weights(float(sqrt_s), wgt.data_ptr(), me.data_ptr(), int(nevt),
+                                    w.data_ptr() if w is not None else None, stats.data_ptr(),
+                                    _stream_handle(stream)))
+    return (w[:nevt] if w is not None else None), stats
+
+
+def unweight(w, r, w_ref, nevt: Optional[int] = None, stream=None):
+    """Hit-or-miss unweighting against the device scalar w_ref (a 1-element
+    float64 tensor, or a view such as stats[2:]): returns the kept event
+    indices (int64 device tensor, increasing); reads the count back to size
+    the result, so this synchronises the stream."""
+    import torch
+    nevt = w.shape[0] if nevt is None else nevt
+    for t in (w, r, w_ref):
+        if t.dtype != torch.float64 or not t.is_contiguous():
+            raise MgmeError(MGME_EINVAL, "weights, random numbers and w_ref must be contiguous float64 tensors")
+    if w.numel() < nevt or r.numel() < nevt or w_ref.numel() < 1:
+        raise MgmeError(MGME_EINVAL, "tensor too short")
+    idx = torch.empty(max(nevt, 1), dtype=torch.int64, device=w.device)
+    nkept = torch.empty(1, dtype=torch.int64, device=w.device)
+    _check(lib().mgme_unweight(w.data_ptr(), r.data_ptr(), int(nevt), w_ref.data_ptr(), idx.data_ptr(),
+                               nkept.data_ptr(), _stream_handle(stream)))
+    return idx[: int(nkept.item())]
 
 
 class Server:

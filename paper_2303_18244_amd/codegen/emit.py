@@ -341,12 +341,14 @@ def emit_ee_process(name: str, pdg: List[int]) -> Dict:
     return meta
 
 
-KERNEL_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}.
+KERNEL_HEADER_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}.
 // {n_diagrams} Feynman diagrams ({n_terms} colour/Lorentz terms), {ncol} colour flows,
 // {n_currents} shared off-shell currents and {n_amps} amplitude vertices per helicity.
+#pragma once
 #include "../helamp.h"
 #include "../me_kernel.h"
 #include "../colour_mfma.h"
+#include "../events.h"
 
 namespace mgme {{
 namespace {name} {{
@@ -358,14 +360,24 @@ constexpr int NCOL = {ncol};
 // MODE 0: |M|^2 summed over the good helicities into out[e];
 // MODE 1: each helicity's contribution into out[ih*ldo + e];
 // MODE 2: the colour-flow vector J of every helicity into
-//         Jout[(ih*NCOL + s)*ldo + e] (single precision) for the matrix-core colour sum.
+//         Jout[(ih*NCOL + s)*ldo + e] (single precision) for the matrix-core colour sum;
+// MODE 3: as MODE 0, and for the helicity and colour choice each helicity's
+//         |M_h|^2 (before normalisation) into aux[ih*lda + e] and
+//         sum_h |J_s|^2 into aux[(nhel + s)*lda + e] (accumulated in LDS).
 template <typename T, int MODE, typename TC = double>
 __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restrict__ mom, long long nevt,
                                                           long long ld, const MeArgs args,
                                                           double* __restrict__ out, long long ldo,
-                                                          float2* __restrict__ Jout) {{
+                                                          float2* __restrict__ Jout, double* __restrict__ aux,
+                                                          long long lda) {{
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nevt) return;
+  // per-lane jamp^2 accumulators (MODE 3), [flow][lane of the block]
+  __shared__ double j2[MODE == 3 ? NCOL * MGME_ME_BLOCK : 1];
+  if constexpr (MODE == 3) {{
+#pragma unroll
+    for (int s = 0; s < NCOL; ++s) j2[s * MGME_ME_BLOCK + threadIdx.x] = 0.0;
+  }}
   double p[NEXT][4];
 #pragma unroll
   for (int i = 0; i < NEXT; ++i)
@@ -392,25 +404,47 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
         Jout[((long long)ih * NCOL + s) * ldo + e] = make_float2((float)J[s].re, (float)J[s].im);
     }} else {{
 {colour}
-      if (MODE == 1) out[(long long)ih * ldo + e] = me * args.factor;
-      else total += me;
+      if constexpr (MODE == 1) {{
+        out[(long long)ih * ldo + e] = me * args.factor;
+      }} else {{
+        total += me;
+        if constexpr (MODE == 3) {{
+          aux[(long long)ih * lda + e] = me;
+#pragma unroll
+          for (int s = 0; s < NCOL; ++s)
+            j2[s * MGME_ME_BLOCK + threadIdx.x] += (double)J[s].re * (double)J[s].re + (double)J[s].im * (double)J[s].im;
+        }}
+      }}
     }}
   }}
-  if (MODE == 0) out[e] = total * args.factor;
+  if constexpr (MODE == 0 || MODE == 3) out[e] = total * args.factor;
+  if constexpr (MODE == 3) {{
+#pragma unroll
+    for (int s = 0; s < NCOL; ++s) aux[(long long)(args.nhel + s) * lda + e] = j2[s * MGME_ME_BLOCK + threadIdx.x];
+  }}
 }}
 
 }}  // namespace {name}
 }}  // namespace mgme
+"""
+
+LAUNCH_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: launcher.
+#include "me_{name}_kernel.h"
+
+extern "C" hipError_t mgme_select_{name}(int prec, const double* mom, long long nevt, long long ld,
+                                          const mgme::MeArgs* args, double* out, const mgme::SelectArgs* sel,
+                                          hipStream_t stream);
 
 extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                           const mgme::MeArgs* args, double* out, long long ldo,
-                                          hipStream_t stream) {{
+                                          const mgme::SelectArgs* sel, hipStream_t stream) {{
   using namespace mgme::{name};
   const dim3 block(MGME_ME_BLOCK);
+  if (sel && prec != 2) return mgme_select_{name}(prec, mom, nevt, ld, args, out, sel, stream);
   if (prec == 2) {{
     // single-precision diagrams write J, the matrix cores form the colour sum
     const int nh = args->nhel;
-    const size_t per_event = (size_t)nh * (NCOL * sizeof(float2) + sizeof(double));
+    const size_t per_event = (size_t)nh * (NCOL * sizeof(float2) + sizeof(double)) + (sel ? NCOL * sizeof(double) : 0);
     long long sub = (long long)(((size_t)4 << 30) / per_event) / 64 * 64;
     if (sub < 64) sub = 64;
     if (sub > nevt) sub = (nevt + 63) / 64 * 64;
@@ -419,39 +453,86 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
     if (err != hipSuccess) return err;
     float2* J = (float2*)ws;
     double* meh = (double*)(ws + (size_t)nh * NCOL * sizeof(float2) * sub);
+    double* jamp2 = meh + (size_t)nh * sub;
     for (long long start = 0; start < nevt && err == hipSuccess; start += sub) {{
       const long long n = (nevt - start < sub) ? nevt - start : sub;
       const dim3 grid((unsigned)((n + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
-      me_kernel<float, 2><<<grid, block, 0, stream>>>(mom + start, n, ld, *args, nullptr, sub, J);
+      me_kernel<float, 2><<<grid, block, 0, stream>>>(mom + start, n, ld, *args, nullptr, sub, J, nullptr, 0);
       err = hipGetLastError();
       if (err == hipSuccess)
         err = mgme::launch_colour_mfma(n, nh, NCOL, J, sub, args->cfrag, per_hel ? out + start : meh,
                                        per_hel ? ldo : sub, per_hel ? args->factor : 1.0, stream);
       if (err == hipSuccess && !per_hel)
         err = mgme::launch_helicity_sum(n, nh, meh, sub, args->factor, out + start, stream);
+      if (err == hipSuccess && sel)
+        err = mgme::launch_jamp2<float>(n, nh, NCOL, (const float*)J, sub, jamp2, sub, stream);
+      if (err == hipSuccess && sel) err = mgme::launch_select(n, args, meh, sub, NCOL, jamp2, sub, sel, start, stream);
     }}
     const hipError_t ferr = hipFreeAsync(ws, stream);
     return err != hipSuccess ? err : ferr;
   }}
   const dim3 grid((unsigned)((nevt + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
   if (prec == 0) {{
-    if (per_hel) me_kernel<double, 1><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
-    else me_kernel<double, 0><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
+    if (per_hel) me_kernel<double, 1><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
+    else me_kernel<double, 0><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
   }} else if (prec == 3) {{
     // double-precision diagrams, single-precision colour algebra
-    if (per_hel) me_kernel<double, 1, float><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
-    else me_kernel<double, 0, float><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
+    if (per_hel)
+      me_kernel<double, 1, float><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
+    else me_kernel<double, 0, float><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
   }} else {{
-    if (per_hel) me_kernel<float, 1><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
-    else me_kernel<float, 0><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr);
+    if (per_hel) me_kernel<float, 1><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
+    else me_kernel<float, 0><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
   }}
   return hipGetLastError();
 }}
 """
 
+SELECT_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: |M|^2 with the
+// helicity and leading-colour choice (kernels instantiated in a unit of their
+// own so that they compile in parallel with the others).
+#include "me_{name}_kernel.h"
 
-def kernel_source(meta: Dict) -> str:
-    return KERNEL_TEMPLATE.format(title=" ".join(str(x) for x in meta["pdg"]), **meta)
+extern "C" hipError_t mgme_select_{name}(int prec, const double* mom, long long nevt, long long ld,
+                                          const mgme::MeArgs* args, double* out, const mgme::SelectArgs* sel,
+                                          hipStream_t stream) {{
+  using namespace mgme::{name};
+  const dim3 block(MGME_ME_BLOCK);
+  const int nh = args->nhel;
+  const size_t per_event = (size_t)(nh + NCOL) * sizeof(double);
+  long long sub = (long long)(((size_t)4 << 30) / per_event) / 64 * 64;
+  if (sub < 64) sub = 64;
+  if (sub > nevt) sub = (nevt + 63) / 64 * 64;
+  double* ws = nullptr;
+  hipError_t err = hipMallocAsync((void**)&ws, per_event * (size_t)sub, stream);
+  if (err != hipSuccess) return err;
+  for (long long start = 0; start < nevt && err == hipSuccess; start += sub) {{
+    const long long n = (nevt - start < sub) ? nevt - start : sub;
+    const dim3 grid((unsigned)((n + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
+    if (prec == 0)
+      me_kernel<double, 3><<<grid, block, 0, stream>>>(mom + start, n, ld, *args, out + start, 0, nullptr, ws, sub);
+    else if (prec == 3)
+      me_kernel<double, 3, float><<<grid, block, 0, stream>>>(mom + start, n, ld, *args, out + start, 0, nullptr, ws,
+                                                               sub);
+    else
+      me_kernel<float, 3><<<grid, block, 0, stream>>>(mom + start, n, ld, *args, out + start, 0, nullptr, ws, sub);
+    err = hipGetLastError();
+    if (err == hipSuccess)
+      err = mgme::launch_select(n, args, ws, sub, NCOL, ws + (size_t)nh * sub, sub, sel, start, stream);
+  }}
+  const hipError_t ferr = hipFreeAsync(ws, stream);
+  return err != hipSuccess ? err : ferr;
+}}
+"""
+
+
+def kernel_sources(meta: Dict) -> Dict[str, str]:
+    """File name -> source for a process evaluated by one fused kernel."""
+    title = " ".join(str(x) for x in meta["pdg"])
+    name = meta["name"]
+    return {f"me_{name}_kernel.h": KERNEL_HEADER_TEMPLATE.format(title=title, **meta),
+            f"me_{name}.hip": LAUNCH_TEMPLATE.format(title=title, name=name),
+            f"me_{name}_sel.hip": SELECT_TEMPLATE.format(title=title, name=name)}
 
 
 CHUNK_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: diagram chunk {chunk} of {n_chunks}.
@@ -513,6 +594,7 @@ COLOUR_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: 
 #include "../helamp.h"
 #include "../me_kernel.h"
 #include "../colour_mfma.h"
+#include "../events.h"
 
 namespace mgme {{
 namespace {name} {{
@@ -584,12 +666,12 @@ __global__ void __launch_bounds__(256) fold_kernel(long long nevt, const MeArgs 
 // the workspace comes from the stream-ordered allocator.
 extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                           const mgme::MeArgs* args, double* out, long long ldo,
-                                          hipStream_t stream) {{
+                                          const mgme::SelectArgs* sel, hipStream_t stream) {{
   using namespace mgme::{name};
   const int nh = args->nhel;
   const int dprec = (prec == 0 || prec == 3) ? 0 : 1;  // diagram precision
   const size_t tsize = dprec == 0 ? sizeof(mgme::cx<double>) : sizeof(mgme::cx<float>);
-  const size_t per_event = (size_t)nh * ((NCOL + NOV) * tsize + sizeof(double));
+  const size_t per_event = (size_t)nh * ((NCOL + NOV) * tsize + sizeof(double)) + (sel ? NCOL * sizeof(double) : 0);
   const size_t budget = (size_t){workspace_bytes};
   long long sub = (long long)(budget / per_event) / 64 * 64;
   if (sub < 64) sub = 64;
@@ -602,6 +684,7 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
   void* Jbuf = ws;
   void* Ovbuf = ws + (size_t)nh * NCOL * tsize * sub;
   double* meh = (double*)(ws + (size_t)nh * (NCOL + NOV) * tsize * sub);
+  double* jamp2 = meh + (size_t)nh * sub;  // helicity and colour choice only
   const double factor = args->factor;
   for (long long start = 0; start < nevt && err == hipSuccess; start += sub) {{
     const long long n = (nevt - start < sub) ? nevt - start : sub;
@@ -629,6 +712,12 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
     }}
     if (err == hipSuccess) err = hipGetLastError();
     if (err == hipSuccess && !per_hel) err = mgme::launch_helicity_sum(n, nh, meh, sub, factor, out + start, stream);
+    if (err == hipSuccess && sel) {{
+      // J now holds every flow (overflow slots folded in by the colour step)
+      err = dprec == 0 ? mgme::launch_jamp2<double>(n, nh, NCOL, (const double*)Jbuf, sub, jamp2, sub, stream)
+                       : mgme::launch_jamp2<float>(n, nh, NCOL, (const float*)Jbuf, sub, jamp2, sub, stream);
+      if (err == hipSuccess) err = mgme::launch_select(n, args, meh, sub, NCOL, jamp2, sub, sel, start, stream);
+    }}
   }}
   const hipError_t ferr = hipFreeAsync(ws, stream);
   return err != hipSuccess ? err : ferr;

@@ -26,9 +26,21 @@ struct MeArgs {
   int hel[MGME_MAX_HEL];    // helicity codes: bit (n_ext-1-leg) set for helicity +1
 };
 
+// Random numbers and results of the per-event helicity and colour choice
+// (device arrays indexed by event).
+struct SelectArgs {
+  const double* r_hel;  // uniform in (0,1): helicity choice
+  const double* r_col;  // uniform in (0,1): colour-flow choice
+  int* hel;             // chosen helicity code
+  int* col;             // chosen colour flow (basis index)
+};
+
 // prec: 0 FP64, 1 FP32 diagrams, 2 FP32 diagrams + 16-bit matrix-core colour sum,
-// 3 FP64 diagrams + FP32 colour algebra.
+// 3 FP64 diagrams + FP32 colour algebra.  per_hel: per-helicity output with
+// leading dimension ldo.  sel: when not NULL, also choose a helicity and a
+// colour flow per event (per_hel must be 0).
 using LaunchFn = hipError_t (*)(int prec, int per_hel, const double* mom, long long nevt, long long ld,
-                                const MeArgs* args, double* out, long long ldo, hipStream_t stream);
+                                const MeArgs* args, double* out, long long ldo, const SelectArgs* sel,
+                                hipStream_t stream);
 
 }  // namespace mgme

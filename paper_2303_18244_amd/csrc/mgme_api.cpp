@@ -15,6 +15,7 @@
 #include "colour_mfma.h"
 #include "me_kernel.h"
 #include "rambo.h"
+#include "events.h"
 #include "registry.h"
 
 struct mgme_process {
@@ -115,7 +116,7 @@ int calibrate(mgme_process* p) {
   for (int i = 0; i < nhel; ++i) all.hel[i] = i;
   rc = launch_rambo_checked(p, sqrt_s, 1ull, 0ull, nev, nev, d_mom, nullptr, nullptr);
   if (rc == MGME_OK) {
-    e = p->entry->launch(0, 1, d_mom, nev, nev, &all, d_out, nev, nullptr);
+    e = p->entry->launch(0, 1, d_mom, nev, nev, &all, d_out, nev, nullptr, nullptr);
     if (e != hipSuccess) rc = hip_fail(e, "calibration launch");
   }
   if (rc == MGME_OK) {
@@ -350,7 +351,7 @@ int mgme_matrix_element(const mgme_process* proc, const double* d_mom, long long
   if (nevt == 0) return MGME_OK;
   if ((rc = select_device(proc->device)) != MGME_OK) return rc;
   const hipError_t e =
-      proc->entry->launch(precision, 0, d_mom, nevt, ld, &proc->args, d_me, 0, (hipStream_t)hip_stream);
+      proc->entry->launch(precision, 0, d_mom, nevt, ld, &proc->args, d_me, 0, nullptr, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "matrix element launch");
   return MGME_OK;
 }
@@ -367,8 +368,62 @@ int mgme_matrix_element_per_helicity(const mgme_process* proc, const double* d_m
   mgme::MeArgs all = proc->args;
   all.nhel = 1 << proc->entry->n_ext;
   for (int i = 0; i < all.nhel; ++i) all.hel[i] = i;
-  const hipError_t e = proc->entry->launch(precision, 1, d_mom, nevt, ld, &all, d_out, ldo, (hipStream_t)hip_stream);
+  const hipError_t e =
+      proc->entry->launch(precision, 1, d_mom, nevt, ld, &all, d_out, ldo, nullptr, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "matrix element launch");
+  return MGME_OK;
+}
+
+int mgme_select(const mgme_process* proc, const double* d_mom, long long nevt, long long ld, int precision,
+                const double* d_r_hel, const double* d_r_col, double* d_me, int* d_hel, int* d_col,
+                void* hip_stream) {
+  int rc = check_batch(proc, d_mom, d_me, nevt, ld);
+  if (rc != MGME_OK) return rc;
+  if (nevt > 0 && (!d_r_hel || !d_r_col || !d_hel || !d_col)) return fail(MGME_EINVAL, "NULL argument");
+  if (!valid_precision(precision)) return fail(MGME_EINVAL, "unknown precision");
+  if ((rc = check_pending("mgme_select")) != MGME_OK) return rc;
+  if (nevt == 0) return MGME_OK;
+  if ((rc = select_device(proc->device)) != MGME_OK) return rc;
+  const mgme::SelectArgs sel{d_r_hel, d_r_col, d_hel, d_col};
+  const hipError_t e =
+      proc->entry->launch(precision, 0, d_mom, nevt, ld, &proc->args, d_me, 0, &sel, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "matrix element launch");
+  return MGME_OK;
+}
+
+int mgme_event_weights(double sqrt_s, const double* d_wgt, const double* d_me, long long nevt, double* d_w,
+                       double* d_stats, void* hip_stream) {
+  if (nevt < 0) return fail(MGME_EINVAL, "nevt < 0");
+  if (!d_stats || (nevt > 0 && (!d_wgt || !d_me))) return fail(MGME_EINVAL, "NULL argument");
+  if (!std::isfinite(sqrt_s) || !(sqrt_s > 0.0)) return fail(MGME_EINVAL, "sqrt_s must be positive");
+  int rc = check_pending("mgme_event_weights");
+  if (rc != MGME_OK) return rc;
+  const hipStream_t stream = (hipStream_t)hip_stream;
+  double* part = nullptr;
+  hipError_t e = hipMallocAsync((void**)&part, sizeof(double) * 3 * mgme::weights_partials(nevt), stream);
+  if (e != hipSuccess) return hip_fail(e, "workspace");
+  e = mgme::launch_event_weights(nevt, d_wgt, d_me, mgme::weight_factor(sqrt_s), d_w, part, d_stats, stream);
+  const hipError_t fe = hipFreeAsync(part, stream);
+  if (e != hipSuccess) return hip_fail(e, "event weights launch");
+  if (fe != hipSuccess) return hip_fail(fe, "workspace");
+  return MGME_OK;
+}
+
+int mgme_unweight(const double* d_w, const double* d_r, long long nevt, const double* d_w_ref, long long* d_idx,
+                  long long* d_nkept, void* hip_stream) {
+  if (nevt < 0) return fail(MGME_EINVAL, "nevt < 0");
+  if (!d_w_ref || !d_nkept || (nevt > 0 && (!d_w || !d_r || !d_idx))) return fail(MGME_EINVAL, "NULL argument");
+  int rc = check_pending("mgme_unweight");
+  if (rc != MGME_OK) return rc;
+  const hipStream_t stream = (hipStream_t)hip_stream;
+  const long long nt = mgme::unweight_tiles(nevt);
+  long long* tiles = nullptr;
+  hipError_t e = hipMallocAsync((void**)&tiles, sizeof(long long) * 2 * (nt > 0 ? nt : 1), stream);
+  if (e != hipSuccess) return hip_fail(e, "workspace");
+  e = mgme::launch_unweight(nevt, d_w, d_r, d_w_ref, d_idx, d_nkept, tiles, stream);
+  const hipError_t fe = hipFreeAsync(tiles, stream);
+  if (e != hipSuccess) return hip_fail(e, "unweighting launch");
+  if (fe != hipSuccess) return hip_fail(fe, "workspace");
   return MGME_OK;
 }
 

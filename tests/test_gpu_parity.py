@@ -69,6 +69,24 @@ def _host(mom, nevt):
     return mom[:, :, :nevt].cpu().numpy().transpose(2, 0, 1).copy()
 
 
+_EVENTS = {}
+
+
+def _events(oracle_mod, name, n, seed=SEED):
+    """The oracle's RAMBO events (seed, events 0..n-1) as the common input of
+    both sides: ([n, n_ext, 4] host array, [n_ext, 4, n] device tensor).
+    Nothing computed by the GPU path is ever handed to the oracle."""
+    torch = _torch()
+    key = (name, n, seed)
+    if key not in _EVENTS:
+        pdg = oracle_mod.PROCESSES[name]
+        host, _ = oracle_mod.rambo(_masses(pdg), CASES[name][2], seed, 0, n)
+        dev = torch.from_numpy(np.ascontiguousarray(host.transpose(1, 2, 0))).to("cuda")
+        _EVENTS.clear()  # keep at most one batch resident
+        _EVENTS[key] = (host, dev)
+    return _EVENTS[key]
+
+
 def _masses(pdg):
     return [173.0 if abs(x) == 6 else 0.0 for x in pdg[2:]]
 
@@ -99,24 +117,24 @@ def test_rambo_matches_oracle(lib_procs, oracle_mod, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_fp64_matches_oracle(lib_procs, oracle_procs, name):
+def test_fp64_matches_oracle(lib_procs, oracle_procs, oracle_mod, name):
     torch = _torch()
     P = _proc(lib_procs, name)
     n, _, sq = CASES[name]
-    mom, _ = P.rambo(sq, SEED, 0, n)
+    host, mom = _events(oracle_mod, name, n)
     me = P.matrix_element(mom).cpu().numpy()
-    rel = _check_fp64(me, _host(mom, n), oracle_procs[name])
+    rel = _check_fp64(me, host, oracle_procs[name])
     print(f"{name} FP64 vs oracle on {n} events: max rel {rel.max():.2e}, median {np.median(rel):.2e}")
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_fp32_accuracy(lib_procs, oracle_procs, name):
+def test_fp32_accuracy(lib_procs, oracle_procs, oracle_mod, name):
     torch = _torch()
     P = _proc(lib_procs, name)
     n, _, sq = CASES[name]
-    mom, _ = P.rambo(sq, SEED, 0, n)
+    host, mom = _events(oracle_mod, name, n)
     me = P.matrix_element(mom, precision=1).cpu().numpy()
-    ref = oracle_procs[name].me(_host(mom, n), nthreads=NTHREADS)
+    ref = oracle_procs[name].me(host, nthreads=NTHREADS)
     rel = np.abs(me / ref - 1.0)
     mean_rel = abs(me.mean() / ref.mean() - 1.0)
     print(f"{name} FP32 vs oracle on {n} events: batch-mean {mean_rel:.2e}, median {np.median(rel):.2e}, "
@@ -126,16 +144,16 @@ def test_fp32_accuracy(lib_procs, oracle_procs, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_mixed_accuracy(lib_procs, oracle_procs, name):
+def test_mixed_accuracy(lib_procs, oracle_procs, oracle_mod, name):
     """Single-precision diagrams with the 16-bit matrix-core colour sum."""
     torch = _torch()
     import paper_2303_18244_amd as M
 
     P = _proc(lib_procs, name)
     n, _, sq = CASES[name]
-    mom, _ = P.rambo(sq, SEED, 0, n)
+    host, mom = _events(oracle_mod, name, n)
     me = P.matrix_element(mom, precision=M.MIXED).cpu().numpy()
-    ref = oracle_procs[name].me(_host(mom, n), nthreads=NTHREADS)
+    ref = oracle_procs[name].me(host, nthreads=NTHREADS)
     rel = np.abs(me / ref - 1.0)
     mean_rel = abs(me.mean() / ref.mean() - 1.0)
     print(f"{name} mixed vs oracle on {n} events: batch-mean {mean_rel:.2e}, median {np.median(rel):.2e}, "
@@ -145,7 +163,7 @@ def test_mixed_accuracy(lib_procs, oracle_procs, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_fp64_diagrams_fp32_colour_accuracy(lib_procs, oracle_procs, name):
+def test_fp64_diagrams_fp32_colour_accuracy(lib_procs, oracle_procs, oracle_mod, name):
     """The paper's mixed mode: double-precision diagrams, single-precision
     colour algebra (section 3).  Same criterion as the other reduced-precision
     modes; the error comes from the colour quadratic form alone, so it is also
@@ -155,9 +173,9 @@ def test_fp64_diagrams_fp32_colour_accuracy(lib_procs, oracle_procs, name):
 
     P = _proc(lib_procs, name)
     n, _, sq = CASES[name]
-    mom, _ = P.rambo(sq, SEED, 0, n)
+    host, mom = _events(oracle_mod, name, n)
     me = P.matrix_element(mom, precision=M.FP64_FP32COLOUR).cpu().numpy()
-    ref = oracle_procs[name].me(_host(mom, n), nthreads=NTHREADS)
+    ref = oracle_procs[name].me(host, nthreads=NTHREADS)
     rel = np.abs(me / ref - 1.0)
     mean_rel = abs(me.mean() / ref.mean() - 1.0)
     print(f"{name} FP64 diagrams + FP32 colour vs oracle on {n} events: batch-mean {mean_rel:.2e}, "
@@ -167,44 +185,47 @@ def test_fp64_diagrams_fp32_colour_accuracy(lib_procs, oracle_procs, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_full_size_sampled(lib_procs, oracle_procs, name):
-    """The configuration's full batch in one launch: sampled events against the
-    oracle, and the leading events bitwise equal to a small batch (no
-    dependence on the batch size or on the launch grid)."""
+def test_full_size_sampled(lib_procs, oracle_procs, oracle_mod, name):
+    """The configuration's full batch in one launch (the benchmark's launch):
+    sampled events against the oracle, and the leading events bitwise equal
+    to a small batch (no dependence on the batch size or on the launch grid).
+    RAMBO at the full size on sampled events against the oracle's."""
     torch = _torch()
     P = _proc(lib_procs, name)
     n_small, n_full, sq = CASES[name]
-    mom, _ = P.rambo(sq, SEED, 0, n_full)
+    host, mom = _events(oracle_mod, name, n_full)
     me = P.matrix_element(mom).cpu().numpy()
     rng = np.random.default_rng(5)
     k = 24 if name == "gg_ttggg" else 96
     idx = np.unique(np.concatenate([rng.choice(n_full, k, replace=False), [0, n_full - 1]]))
-    mom_h = mom[:, :, idx].cpu().numpy().transpose(2, 0, 1).copy()
-    _check_fp64(me[idx], mom_h, oracle_procs[name])
-    small, _ = P.rambo(sq, SEED, 0, 333)
-    me_small = P.matrix_element(small).cpu().numpy()
+    _check_fp64(me[idx], host[idx], oracle_procs[name])
+    me_small = P.matrix_element(mom[:, :, :333].contiguous()).cpu().numpy()
     assert np.array_equal(me_small, me[:333])
     assert np.all(np.isfinite(me)) and np.all(me > 0)
+    gmom, gw = P.rambo(sq, SEED, 0, n_full)
+    gsel = gmom[:, :, idx].cpu().numpy().transpose(2, 0, 1)
+    for j, e in enumerate(idx):
+        om, ow = oracle_mod.rambo(_masses(P.pdg), sq, SEED, int(e), 1)
+        assert np.abs(gsel[j] - om[0]).max() <= 1e-12 * sq
+        assert abs(gw[int(e)].item() / ow[0] - 1.0) <= 1e-11
 
 
 @pytest.mark.parametrize("name", list(CASES))
-def test_good_helicities_match_oracle(lib_procs, oracle_procs, name):
+def test_good_helicities_match_oracle(lib_procs, oracle_procs, oracle_mod, name):
     """Good helicities = helicities with a non-zero FP64 contribution on at
     least one of 64 calibration events (seed 1); per-helicity values agree."""
     torch = _torch()
     P = _proc(lib_procs, name)
-    sq = CASES[name][2]
-    mom, _ = P.rambo(sq, 1, 0, 64)
-    host = _host(mom, 64)
+    host, mom = _events(oracle_mod, name, 64, seed=1)
     O = oracle_procs[name]
-    per = np.array([O.me_hel(host[e]) for e in range(0, 64, 1 if P.n_ext < 7 else 16)])
+    step = 1 if P.n_ext < 7 else 16
+    per = np.array([O.me_hel(host[e]) for e in range(0, 64, step)])
     expected = [h for h in range(1 << P.n_ext) if np.any(per[:, h] != 0.0)]
     if P.n_ext < 7:
         assert P.good_helicities() == expected
     if name == "ee_mumu":
         assert len(expected) == 4
     gpu = P.matrix_element_per_helicity(mom).cpu().numpy()  # [n_hel, 64]
-    step = 1 if P.n_ext < 7 else 16
     for j, e in enumerate(range(0, 64, step)):
         # helicities that vanish analytically come out as rounding noise far
         # below the others; compare them on the scale of the event's total

@@ -60,6 +60,18 @@ def test_cross_section_ee_photon(oracle_mod):
     assert st[2] == w.max() and np.all(w > 0)
 
 
+def test_weight_sums_exactly_rounded(oracle_mod):
+    """Heavy-tailed weights: the sums equal the exactly rounded sums."""
+    rng = np.random.default_rng(4)
+    n = 200000
+    wgt = np.exp(rng.normal(-12.0, 0.5, n))
+    me = np.exp(rng.normal(-20.0, 3.0, n))
+    w, st = oracle_mod.event_weights(wgt, me, 1500.0)
+    assert abs(st[0] / math.fsum(w.tolist()) - 1.0) <= 2.3e-16
+    assert abs(st[1] / math.fsum((w * w).tolist()) - 1.0) <= 4.5e-16  # w*w rounded once more in fsum's input
+    assert st[2] == w.max()
+
+
 def test_cross_section_gg_tt_combridge(oracle_mod):
     P = oracle_mod.Process(oracle_mod.PROCESSES["gg_tt"])
     n = 40000

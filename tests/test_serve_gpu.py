@@ -18,7 +18,7 @@ def test_mix_equals_alone():
     plan = [("gg_tt", 5000, M.FP64), ("gg_ttgg", 3000, M.MIXED), ("gg_ttggg", 300, M.FP64),
             ("gg_ttg", 20000, M.FP32), ("gg_ttgg", 7001, M.FP64), ("gg_ttggg", 197, M.MIXED),
             ("ee_mumu", 4000, M.FP64), ("gg_ttg", 1500, M.MIXED), ("gg_tt", 65536, M.FP32),
-            ("gg_ttgg", 1024, M.FP32)]
+            ("gg_ttgg", 1024, M.FP32), ("gg_ttgg", 2000, M.FP64_FP32COLOUR)]
     inputs, refs = [], []
     for k, (name, n, prec) in enumerate(plan):
         P = procs[name]
