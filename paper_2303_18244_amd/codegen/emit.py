@@ -84,9 +84,14 @@ class GGBody:
     helicity configuration: external wavefunctions, the currents each
     amplitude needs (computed at first use), and the amplitude values."""
 
-    def __init__(self, sched: Schedule, pdg: List[int], em: Emitter, fresh_externals: bool = True):
+    def __init__(self, sched: Schedule, pdg: List[int], em: Emitter, fresh_externals: bool = True,
+                 lds_momenta: bool = False):
+        """lds_momenta: the momenta are read from the lane's LDS rows (fused
+        kernels) instead of the register array q (one lane per event and
+        helicity in the staged kernels)."""
         self.sched = sched
         self.em = em
+        self.lds = lds_momenta
         n_ext = len(pdg)
         incoming = [i < 2 for i in range(n_ext)]
         q_leg = pdg.index(6)
@@ -94,13 +99,19 @@ class GGBody:
         self.fresh_fn: Dict[str, str] = {}
         for i in range(n_ext):
             lam = f"((hc >> {n_ext - 1 - i}) & 1 ? 1 : -1)"
+            if self.lds:
+                em.w(f"double q{i}[4]; load_mom_lds<MGME_ME_BLOCK>(q{i}, smom, lane, {i});")
+                qi = f"q{i}"
+            else:
+                qi = f"q[{i}]"
+            cq = "" if self.lds else "const "
             if pdg[i] == 21:
-                em.w(f"const wf<T> x{i} = ext_vec<T>(q[{i}], {lam}, {'false' if incoming[i] else 'true'});")
+                em.w(f"{cq}wf<T> x{i} = ext_vec<T>({qi}, {lam}, {'false' if incoming[i] else 'true'});")
                 self.fresh_fn[f"x{i}"] = "fresh_pol"
             elif i == q_leg:
-                em.w(f"const wf<T> x{i} = ext_bra<T>(q[{i}], mt, {lam}, false);")
+                em.w(f"{cq}wf<T> x{i} = ext_bra<T>({qi}, mt, {lam}, false);")
             else:
-                em.w(f"const wf<T> x{i} = ext_ket<T>(q[{i}], mt, {lam}, true);")
+                em.w(f"{cq}wf<T> x{i} = ext_ket<T>({qi}, mt, {lam}, true);")
             self.names[("X", i)] = f"x{i}"
             if not fresh_externals:
                 self.fresh_fn[f"x{i}"] = ""
@@ -109,11 +120,32 @@ class GGBody:
 
     def fr(self, v: str) -> str:
         fn = self.fresh_fn.get(v, "fresh")
+        if self.lds:
+            return v  # laundered in place by prep()
         return f"{fn}({v})" if fn else v
 
+    def prep(self, names) -> str:
+        """Statements giving the inputs of the next routine call new
+        identities in place (fused kernels); empty otherwise."""
+        if not self.lds:
+            return ""
+        out = []
+        for v in dict.fromkeys(names):
+            fn = self.fresh_fn.get(v, "fresh")
+            if fn == "fresh":
+                out.append(f"launder({v});")
+            elif fn == "fresh_pol":
+                out.append(f"launder_pol({v});")
+        return " ".join(out) + (" " if out else "")
+
+    def fm(self, out: str, mask: int) -> str:
+        """Statement computing the flow-in momentum of the legs in `mask`."""
+        if self.lds:
+            return f"flow_momentum_lds<{mask}u, {self.inmask}u, NEXT, MGME_ME_BLOCK>({out}, smom, lane);"
+        return f"flow_momentum<{mask}u, {self.inmask}u, NEXT>({out}, q);"
+
     def mom(self, var: str, mask: int) -> str:
-        return (f"double {var}d[4]; flow_momentum<{mask}u, {self.inmask}u, NEXT>({var}d, q); "
-                f"T {var}[4]; to_t({var}, {var}d);")
+        return f"double {var}d[4]; {self.fm(var + 'd', mask)} T {var}[4]; to_t({var}, {var}d);"
 
     def leg_mask(self, k) -> int:
         return self.sched.currents[k].mask if k[0] != "X" else 1 << k[1]
@@ -127,20 +159,21 @@ class GGBody:
         v = f"w{self.counter}"
         self.counter += 1
         em.w(f"wf<T> {v};")
+        pre = self.prep(ins)
         if cur.routine == "vvv_vec":
             c1, c2 = cur.tree.children
-            em.w(f"{{ {mom('k1', c1.mask)} {mom('k2', c2.mask)}")
+            em.w(f"{{ {pre}{mom('k1', c1.mask)} {mom('k2', c2.mask)}")
             em.w("  const double Pd[4] = {k1d[0] + k2d[0], k1d[1] + k2d[1], k1d[2] + k2d[2], k1d[3] + k2d[3]};")
             em.w(f"  {v} = vvv_vec<T>({fr(ins[0])}, k1, {fr(ins[1])}, k2, (T)inv_virt(Pd, 0.0)); }}")
         elif cur.routine == "vvvv_vec":
-            em.w(f"{{ double Pd[4]; flow_momentum<{cur.mask}u, {self.inmask}u, NEXT>(Pd, q);")
+            em.w(f"{{ {pre}double Pd[4]; {self.fm('Pd', cur.mask)}")
             em.w(f"  {v} = vvvv_vec<T, {cur.tree.s}>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])}, "
                  f"(T)inv_virt(Pd, 0.0)); }}")
         elif cur.routine in ("ket_prop", "bra_prop"):
-            em.w(f"{{ {mom('P', cur.mask)}")
+            em.w(f"{{ {pre}{mom('P', cur.mask)}")
             em.w(f"  {v} = {cur.routine}<T>({fr(ins[0])}, {fr(ins[1])}, P, (T)mt, (T)inv_virt(Pd, mt)); }}")
         elif cur.routine == "ffv_vec":
-            em.w(f"{{ double Pd[4]; flow_momentum<{cur.mask}u, {self.inmask}u, NEXT>(Pd, q);")
+            em.w(f"{{ {pre}double Pd[4]; {self.fm('Pd', cur.mask)}")
             em.w(f"  {v} = ffv_vec<T>({fr(ins[0])}, {fr(ins[1])}, (T)inv_virt(Pd, 0.0)); }}")
         else:
             raise ValueError(cur.routine)
@@ -151,14 +184,15 @@ class GGBody:
         """Opens a block defining `a`, the amplitude value; the caller closes it."""
         em, fr = self.em, self.fr
         ins = [self.need(k) for k in a.inputs]
+        pre = self.prep(ins)
         if a.routine == "ffv_amp":
-            em.w(f"{{ const cx<T> a = ffv_amp<T>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])});")
+            em.w(f"{{ {pre}const cx<T> a = ffv_amp<T>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])});")
         elif a.routine == "vvv_amp":
             m1, m2, m3 = (self.leg_mask(k) for k in a.inputs)
-            em.w(f"{{ {self.mom('k1', m1)} {self.mom('k2', m2)} {self.mom('k3', m3)}")
+            em.w(f"{{ {pre}{self.mom('k1', m1)} {self.mom('k2', m2)} {self.mom('k3', m3)}")
             em.w(f"  const cx<T> a = vvv_amp<T>({fr(ins[0])}, k1, {fr(ins[1])}, k2, {fr(ins[2])}, k3);")
         else:
-            em.w(f"{{ const cx<T> a = vvvv_amp<T, {a.s}>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])}, "
+            em.w(f"{{ {pre}const cx<T> a = vvvv_amp<T, {a.s}>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])}, "
                  f"{fr(ins[3])});")
 
 
@@ -192,7 +226,7 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
     registers and the colour sum runs in the same kernel."""
     n_ext, gluon_legs, terms, n_diag, flows, C, cden, sched = _gg_setup(pdg)
     em = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
-    body = GGBody(sched, pdg, em)
+    body = GGBody(sched, pdg, em, lds_momenta=True)
     ncol = len(flows)
     em.w(f"cx<T> J[{ncol}];")
     em.w(f"for (int s = 0; s < {ncol}; ++s) J[s] = mk<T>((T)0, (T)0);")
@@ -297,10 +331,14 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
         flops_hel += sum(FLOPS[a.routine] + FLOPS["acc"] * len(a.coeffs) for a in chunk)
         flops_hel += sum(sched.currents[k].cost for k in body.names if k[0] != "X")
     assert written == set(range(ncol)), "every flow receives a contribution"
-    flops_hel += 2 * ncol * ncol + 4 * ncol + 2 * (n_rmw + len(overflow_flow)) + 90 * n_ext * n_chunks
+    # executed work, with the currents that several chunks recompute
+    flops_exec = flops_hel + 2 * ncol * ncol + 4 * ncol + 2 * (n_rmw + len(overflow_flow)) + 90 * n_ext * n_chunks
+    # algorithmic work: every current once, as in the fused kernels
+    flops_hel = sched.flops_per_helicity() + 2 * ncol * ncol + 4 * ncol + 90 * n_ext
     overflow_of = [[s for s, f in enumerate(overflow_flow) if f == fl] for fl in range(ncol)]
     return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "",
                     staged=True, chunk_bodies=chunk_bodies, n_overflow=len(overflow_flow), n_rmw=n_rmw,
+                    flops_exec_per_hel=flops_exec,
                     overflow_of=overflow_of, colour_num=[int(v * cden) for row in C for v in row])
 
 
@@ -316,6 +354,8 @@ def emit_ee_process(name: str, pdg: List[int]) -> Dict:
     lines = []
     w = lambda s: lines.append("    " + s)
     lam = lambda i: f"((hc >> {3 - i}) & 1 ? 1 : -1)"
+    w("double q[4][4];")
+    w("for (int i = 0; i < 4; ++i) load_mom_lds<MGME_ME_BLOCK>(q[i], smom, lane, i);")
     w(f"const wf<T> x0 = ext_bra<T>(q[0], 0.0, {lam(0)}, true);   // vbar(e+)")
     w(f"const wf<T> x1 = ext_ket<T>(q[1], 0.0, {lam(1)}, false);  // u(e-)")
     w(f"const wf<T> x2 = ext_ket<T>(q[2], 0.0, {lam(2)}, true);   // v(mu+)")
@@ -372,31 +412,25 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
                                                           long long lda) {{
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nevt) return;
+  const int lane = threadIdx.x;
   // per-lane jamp^2 accumulators (MODE 3), [flow][lane of the block]
   __shared__ double j2[MODE == 3 ? NCOL * MGME_ME_BLOCK : 1];
   if constexpr (MODE == 3) {{
 #pragma unroll
-    for (int s = 0; s < NCOL; ++s) j2[s * MGME_ME_BLOCK + threadIdx.x] = 0.0;
+    for (int s = 0; s < NCOL; ++s) j2[s * MGME_ME_BLOCK + lane] = 0.0;
   }}
-  double p[NEXT][4];
+  // The lane's momenta stay in LDS: every momentum-dependent quantity is
+  // derived again inside the helicity loop where it is needed, instead of
+  // being held in registers across it.
+  __shared__ double smom[NEXT * 4 * MGME_ME_BLOCK];
 #pragma unroll
   for (int i = 0; i < NEXT; ++i)
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) p[i][mu] = mom[(long long)(i * 4 + mu) * ld + e];
+    for (int mu = 0; mu < 4; ++mu) smom[(i * 4 + mu) * MGME_ME_BLOCK + lane] = mom[(long long)(i * 4 + mu) * ld + e];
   const double mt = args.mt;
   double total = 0.0;
   for (int ih = 0; ih < args.nhel; ++ih) {{
     const int hc = args.hel[ih];
-    // Re-derive every momentum-dependent quantity inside the helicity loop
-    // instead of holding all of them in registers across it.
-    double q[NEXT][4];
-#pragma unroll
-    for (int i = 0; i < NEXT; ++i)
-#pragma unroll
-      for (int mu = 0; mu < 4; ++mu) {{
-        q[i][mu] = p[i][mu];
-        asm volatile("" : "+v"(q[i][mu]));
-      }}
 {body}
     if constexpr (MODE == 2) {{
 #pragma unroll

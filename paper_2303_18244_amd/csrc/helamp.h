@@ -33,6 +33,30 @@ template <typename T> __device__ __forceinline__ cx<T> conjg(cx<T> a) { return {
 // i * a
 template <typename T> __device__ __forceinline__ cx<T> timesi(cx<T> a) { return {-a.im, a.re}; }
 
+// Fused multiply-adds.  Sums of complex products are written as chains of
+// these: n products then take 2 multiplies and 4n - 2 FMAs, where the plain
+// expression tree costs 2n multiplies, 2n FMAs and 2(n-1) additions.
+template <typename T> __device__ __forceinline__ T fmaT(T a, T b, T c) {
+  if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+  else return __builtin_fmaf(a, b, c);
+}
+// a * b
+template <typename T> __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {fmaT(a.re, b.re, -(a.im * b.im)), fmaT(a.re, b.im, a.im * b.re)};
+}
+// acc + a * b
+template <typename T> __device__ __forceinline__ cx<T> cfma(cx<T> a, cx<T> b, cx<T> acc) {
+  return {fmaT(a.re, b.re, fmaT(-a.im, b.im, acc.re)), fmaT(a.re, b.im, fmaT(a.im, b.re, acc.im))};
+}
+// acc - a * b
+template <typename T> __device__ __forceinline__ cx<T> cfms(cx<T> a, cx<T> b, cx<T> acc) {
+  return {fmaT(-a.re, b.re, fmaT(a.im, b.im, acc.re)), fmaT(-a.re, b.im, fmaT(-a.im, b.re, acc.im))};
+}
+// acc + s * a, s real
+template <typename T> __device__ __forceinline__ cx<T> sfma(T s, cx<T> a, cx<T> acc) {
+  return {fmaT(s, a.re, acc.re), fmaT(s, a.im, acc.im)};
+}
+
 // Four complex components: a spinor (ket column or bra row) or a
 // contravariant vector.
 template <typename T> struct wf {
@@ -41,11 +65,11 @@ template <typename T> struct wf {
 
 // Minkowski product of two complex vectors (no conjugation).
 template <typename T> __device__ __forceinline__ cx<T> mdot(const wf<T>& a, const wf<T>& b) {
-  return a.c[0] * b.c[0] - a.c[1] * b.c[1] - a.c[2] * b.c[2] - a.c[3] * b.c[3];
+  return cfms(a.c[3], b.c[3], cfms(a.c[2], b.c[2], cfms(a.c[1], b.c[1], cmul(a.c[0], b.c[0]))));
 }
 // Minkowski product of a real vector with a complex vector.
 template <typename T> __device__ __forceinline__ cx<T> mdot(const T k[4], const wf<T>& a) {
-  return k[0] * a.c[0] - k[1] * a.c[1] - k[2] * a.c[2] - k[3] * a.c[3];
+  return sfma(-k[3], a.c[3], sfma(-k[2], a.c[2], sfma(-k[1], a.c[1], k[0] * a.c[0])));
 }
 
 // ---------------------------------------------------------------- externals
@@ -150,36 +174,42 @@ template <typename T> __device__ __forceinline__ blocks2<T> vsigma(const wf<T>& 
 template <typename T> __device__ __forceinline__ blocks2<T> vsigmabar(const wf<T>& V) {
   return {V.c[0] + V.c[3], V.c[1] - timesi(V.c[2]), V.c[1] + timesi(V.c[2]), V.c[0] - V.c[3]};
 }
+// V.sigmabar from V.sigma: the diagonals swap and the off-diagonals change
+// sign (the negation is free as an FMA operand modifier).
+template <typename T> __device__ __forceinline__ blocks2<T> vsigmabar_of(const blocks2<T>& A) {
+  return {A.a11, -A.a01, -A.a10, A.a00};
+}
 
 // ---------------------------------------------------------------- vertices
 // Amplitude bra . Vslash . ket  (quark-gluon vertex, vector coupling).
 template <typename T> __device__ __forceinline__ cx<T> ffv_amp(const wf<T>& bra, const wf<T>& ket, const wf<T>& V) {
-  const blocks2<T> A = vsigma(V), B = vsigmabar(V);
-  const cx<T> u0 = A.a00 * ket.c[2] + A.a01 * ket.c[3];
-  const cx<T> u1 = A.a10 * ket.c[2] + A.a11 * ket.c[3];
-  const cx<T> l0 = B.a00 * ket.c[0] + B.a01 * ket.c[1];
-  const cx<T> l1 = B.a10 * ket.c[0] + B.a11 * ket.c[1];
-  return bra.c[0] * u0 + bra.c[1] * u1 + bra.c[2] * l0 + bra.c[3] * l1;
+  const blocks2<T> A = vsigma(V), B = vsigmabar_of(A);
+  const cx<T> u0 = cfma(A.a01, ket.c[3], cmul(A.a00, ket.c[2]));
+  const cx<T> u1 = cfma(A.a11, ket.c[3], cmul(A.a10, ket.c[2]));
+  const cx<T> l0 = cfma(B.a01, ket.c[1], cmul(B.a00, ket.c[0]));
+  const cx<T> l1 = cfma(B.a11, ket.c[1], cmul(B.a10, ket.c[0]));
+  return cfma(bra.c[3], l1, cfma(bra.c[2], l0, cfma(bra.c[1], u1, cmul(bra.c[0], u0))));
 }
 
 // Off-shell ket: (qslash + m) Vslash ket * den, q the momentum along the fermion arrow.
 template <typename T>
 __device__ __forceinline__ wf<T> ket_prop(const wf<T>& ket, const wf<T>& V, const T q[4], T m, T den) {
-  const blocks2<T> A = vsigma(V), B = vsigmabar(V);
+  const blocks2<T> A = vsigma(V), B = vsigmabar_of(A);
   // x = Vslash ket
-  const cx<T> x0 = A.a00 * ket.c[2] + A.a01 * ket.c[3];
-  const cx<T> x1 = A.a10 * ket.c[2] + A.a11 * ket.c[3];
-  const cx<T> x2 = B.a00 * ket.c[0] + B.a01 * ket.c[1];
-  const cx<T> x3 = B.a10 * ket.c[0] + B.a11 * ket.c[1];
-  // y = (qslash + m) x, q real: q.sigma = [[q0-q3, -q1+iq2],[-q1-iq2, q0+q3]]
-  const T qa = q[0] - q[3], qb = q[0] + q[3];
-  const cx<T> qm = mk<T>(-q[1], q[2]);   // -q1 + i q2
-  const cx<T> qp = mk<T>(-q[1], -q[2]);  // -q1 - i q2
+  const cx<T> x0 = cfma(A.a01, ket.c[3], cmul(A.a00, ket.c[2]));
+  const cx<T> x1 = cfma(A.a11, ket.c[3], cmul(A.a10, ket.c[2]));
+  const cx<T> x2 = cfma(B.a01, ket.c[1], cmul(B.a00, ket.c[0]));
+  const cx<T> x3 = cfma(B.a11, ket.c[1], cmul(B.a10, ket.c[0]));
+  // y = den (qslash + m) x, q real: q.sigma = [[q0-q3, -q1+iq2],[-q1-iq2, q0+q3]];
+  // den is folded into the five real coefficients
+  const T qa = den * (q[0] - q[3]), qb = den * (q[0] + q[3]), dm = den * m;
+  const cx<T> qm = mk<T>(-den * q[1], den * q[2]);   // den (-q1 + i q2)
+  const cx<T> qp = conjg(qm);                        // den (-q1 - i q2)
   wf<T> y;
-  y.c[0] = den * (qa * x2 + qm * x3 + m * x0);
-  y.c[1] = den * (qp * x2 + qb * x3 + m * x1);
-  y.c[2] = den * (qb * x0 - qm * x1 + m * x2);
-  y.c[3] = den * (-qp * x0 + qa * x1 + m * x3);
+  y.c[0] = cfma(qm, x3, sfma(qa, x2, dm * x0));
+  y.c[1] = cfma(qp, x2, sfma(qb, x3, dm * x1));
+  y.c[2] = cfms(qm, x1, sfma(qb, x0, dm * x2));
+  y.c[3] = cfms(qp, x0, sfma(qa, x1, dm * x3));
   return y;
 }
 
@@ -187,33 +217,39 @@ __device__ __forceinline__ wf<T> ket_prop(const wf<T>& ket, const wf<T>& V, cons
 // momentum of the new current).
 template <typename T>
 __device__ __forceinline__ wf<T> bra_prop(const wf<T>& bra, const wf<T>& V, const T P[4], T m, T den) {
-  const blocks2<T> A = vsigma(V), B = vsigmabar(V);
+  const blocks2<T> A = vsigma(V), B = vsigmabar_of(A);
   // x = bra Vslash (row): upper out = bra_lo B, lower out = bra_up A
-  const cx<T> x0 = bra.c[2] * B.a00 + bra.c[3] * B.a10;
-  const cx<T> x1 = bra.c[2] * B.a01 + bra.c[3] * B.a11;
-  const cx<T> x2 = bra.c[0] * A.a00 + bra.c[1] * A.a10;
-  const cx<T> x3 = bra.c[0] * A.a01 + bra.c[1] * A.a11;
-  // y = x (qslash + m) with q = -P: upper out = x_lo (q.sigmabar) + m x_up, lower out = x_up (q.sigma) + m x_lo
-  const T q0 = -P[0], q1 = -P[1], q2 = -P[2], q3 = -P[3];
+  const cx<T> x0 = cfma(bra.c[3], B.a10, cmul(bra.c[2], B.a00));
+  const cx<T> x1 = cfma(bra.c[3], B.a11, cmul(bra.c[2], B.a01));
+  const cx<T> x2 = cfma(bra.c[1], A.a10, cmul(bra.c[0], A.a00));
+  const cx<T> x3 = cfma(bra.c[1], A.a11, cmul(bra.c[0], A.a01));
+  // y = den x (qslash + m) with q = -P: upper out = x_lo (q.sigmabar) + m x_up,
+  // lower out = x_up (q.sigma) + m x_lo; den is folded into the real coefficients
+  const T q0 = -den * P[0], q1 = -den * P[1], q2 = -den * P[2], q3 = -den * P[3], dm = den * m;
   const T qa = q0 - q3, qb = q0 + q3;
-  const cx<T> qm = mk<T>(-q1, q2);   // -q1 + i q2  (q.sigma off-diagonal 01)
-  const cx<T> qp = mk<T>(-q1, -q2);  // -q1 - i q2  (q.sigma off-diagonal 10)
+  const cx<T> qm = mk<T>(-q1, q2);   // den (-q1 + i q2)  (q.sigma off-diagonal 01)
+  const cx<T> qp = conjg(qm);        // den (-q1 - i q2)  (q.sigma off-diagonal 10)
   // q.sigma = [[qa, qm], [qp, qb]], q.sigmabar = [[qb, -qm], [-qp, qa]]
   wf<T> y;
-  y.c[0] = den * (qb * x2 - x3 * qp + m * x0);
-  y.c[1] = den * (-(x2 * qm) + qa * x3 + m * x1);
-  y.c[2] = den * (qa * x0 + x1 * qp + m * x2);
-  y.c[3] = den * (x0 * qm + qb * x1 + m * x3);
+  y.c[0] = cfms(x3, qp, sfma(qb, x2, dm * x0));
+  y.c[1] = cfms(x2, qm, sfma(qa, x3, dm * x1));
+  y.c[2] = cfma(x1, qp, sfma(qa, x0, dm * x2));
+  y.c[3] = cfma(x0, qm, sfma(qb, x1, dm * x3));
   return y;
 }
 
 // Vector current bra gamma^mu ket * den (contravariant index).
 template <typename T> __device__ __forceinline__ wf<T> ffv_vec(const wf<T>& b, const wf<T>& k, T den) {
+  // components 0 and 3 share the pairs p = b0 k2 + b3 k1 and r = b1 k3 + b2 k0
+  const cx<T> p = cfma(b.c[3], k.c[1], cmul(b.c[0], k.c[2]));
+  const cx<T> r = cfma(b.c[2], k.c[0], cmul(b.c[1], k.c[3]));
+  const cx<T> j1 = cfms(b.c[3], k.c[0], cfms(b.c[2], k.c[1], cfma(b.c[1], k.c[2], cmul(b.c[0], k.c[3]))));
+  const cx<T> j2 = cfma(b.c[2], k.c[1], cfms(b.c[3], k.c[0], cfms(b.c[0], k.c[3], cmul(b.c[1], k.c[2]))));
   wf<T> J;
-  J.c[0] = den * (b.c[0] * k.c[2] + b.c[1] * k.c[3] + b.c[2] * k.c[0] + b.c[3] * k.c[1]);
-  J.c[1] = den * (b.c[0] * k.c[3] + b.c[1] * k.c[2] - b.c[2] * k.c[1] - b.c[3] * k.c[0]);
-  J.c[2] = den * timesi(b.c[1] * k.c[2] - b.c[0] * k.c[3] - b.c[3] * k.c[0] + b.c[2] * k.c[1]);
-  J.c[3] = den * (b.c[0] * k.c[2] - b.c[1] * k.c[3] - b.c[2] * k.c[0] + b.c[3] * k.c[1]);
+  J.c[0] = den * (p + r);
+  J.c[1] = den * j1;
+  J.c[2] = den * timesi(j2);
+  J.c[3] = den * (p - r);
   return J;
 }
 
@@ -247,11 +283,11 @@ __device__ __forceinline__ wf<T> vvv_vec(const wf<T>& V1, const T k1[4], const w
     a[mu] = k1[mu] + 2 * k2[mu];
     b[mu] = 2 * k1[mu] + k2[mu];
   }
-  const cx<T> v12 = mdot(V1, V2);
-  const cx<T> s1 = mdot(a, V1);
-  const cx<T> s2 = mdot(b, V2);
+  const cx<T> v12 = den * mdot(V1, V2);
+  const cx<T> s1 = den * mdot(a, V1);
+  const cx<T> s2 = den * mdot(b, V2);
   wf<T> W;
-  for (int mu = 0; mu < 4; ++mu) W.c[mu] = den * (d[mu] * v12 + V2.c[mu] * s1 - V1.c[mu] * s2);
+  for (int mu = 0; mu < 4; ++mu) W.c[mu] = cfms(V1.c[mu], s2, cfma(V2.c[mu], s1, d[mu] * v12));
   return W;
 }
 
@@ -265,7 +301,7 @@ __device__ __forceinline__ cx<T> vvv_amp(const wf<T>& V1, const T k1[4], const w
     d23[mu] = k2[mu] - k3[mu];
     d31[mu] = k3[mu] - k1[mu];
   }
-  return mdot(V1, V2) * mdot(d12, V3) + mdot(V2, V3) * mdot(d23, V1) + mdot(V3, V1) * mdot(d31, V2);
+  return cfma(mdot(V3, V1), mdot(d31, V2), cfma(mdot(V2, V3), mdot(d23, V1), cmul(mdot(V1, V2), mdot(d12, V3))));
 }
 
 // Four-gluon vertex, one of its three colour structures, leg 4 off shell.
@@ -274,22 +310,22 @@ __device__ __forceinline__ wf<T> vvvv_vec(const wf<T>& V1, const wf<T>& V2, cons
   wf<T> W;
   if (S == 0) {  // (V1.V3) V2 - (V2.V3) V1
     const cx<T> a = den * mdot(V1, V3), b = den * mdot(V2, V3);
-    for (int mu = 0; mu < 4; ++mu) W.c[mu] = a * V2.c[mu] - b * V1.c[mu];
+    for (int mu = 0; mu < 4; ++mu) W.c[mu] = cfms(b, V1.c[mu], cmul(a, V2.c[mu]));
   } else if (S == 1) {  // (V1.V2) V3 - (V2.V3) V1
     const cx<T> a = den * mdot(V1, V2), b = den * mdot(V2, V3);
-    for (int mu = 0; mu < 4; ++mu) W.c[mu] = a * V3.c[mu] - b * V1.c[mu];
+    for (int mu = 0; mu < 4; ++mu) W.c[mu] = cfms(b, V1.c[mu], cmul(a, V3.c[mu]));
   } else {  // (V1.V2) V3 - (V1.V3) V2
     const cx<T> a = den * mdot(V1, V2), b = den * mdot(V1, V3);
-    for (int mu = 0; mu < 4; ++mu) W.c[mu] = a * V3.c[mu] - b * V2.c[mu];
+    for (int mu = 0; mu < 4; ++mu) W.c[mu] = cfms(b, V2.c[mu], cmul(a, V3.c[mu]));
   }
   return W;
 }
 
 template <typename T, int S>
 __device__ __forceinline__ cx<T> vvvv_amp(const wf<T>& V1, const wf<T>& V2, const wf<T>& V3, const wf<T>& V4) {
-  if (S == 0) return mdot(V1, V3) * mdot(V2, V4) - mdot(V1, V4) * mdot(V2, V3);
-  if (S == 1) return mdot(V1, V2) * mdot(V3, V4) - mdot(V1, V4) * mdot(V2, V3);
-  return mdot(V1, V2) * mdot(V3, V4) - mdot(V1, V3) * mdot(V2, V4);
+  if (S == 0) return cfms(mdot(V1, V4), mdot(V2, V3), cmul(mdot(V1, V3), mdot(V2, V4)));
+  if (S == 1) return cfms(mdot(V1, V4), mdot(V2, V3), cmul(mdot(V1, V2), mdot(V3, V4)));
+  return cfms(mdot(V1, V3), mdot(V2, V4), cmul(mdot(V1, V2), mdot(V3, V4)));
 }
 
 // Adds c * a to J for a Gaussian-integer c in {+-1, +-i} (or small integers).
@@ -366,13 +402,67 @@ __device__ __forceinline__ void flow_momentum(double out[4], const double (&q)[N
   }
 }
 
+// In-place forms of the two above: the variable itself gets the new
+// identity, so no copy is needed when it is used again later.  Emitted
+// before every routine call for each of its inputs.
+template <typename T> __device__ __forceinline__ void launder(wf<T>& w) {
+  if constexpr (sizeof(T) == 8)
+    asm volatile("" : "+v"(w.c[0].re), "+v"(w.c[0].im), "+v"(w.c[1].re), "+v"(w.c[1].im), "+v"(w.c[2].re),
+                 "+v"(w.c[2].im), "+v"(w.c[3].re), "+v"(w.c[3].im));
+}
+template <typename T> __device__ __forceinline__ void launder_pol(wf<T>& w) {
+  if constexpr (sizeof(T) == 8) {
+    asm volatile("" : "+v"(w.c[1].re), "+v"(w.c[1].im), "+v"(w.c[2].re), "+v"(w.c[2].im), "+v"(w.c[3].re));
+    w.c[0] = mk<T>((T)0, (T)0);
+    w.c[3].im = (T)0;
+  }
+}
+
+// Momenta staged per lane in LDS: component mu of leg i at
+// smom[(i*4 + mu)*BLOCK + lane].  The lane index is laundered on every use,
+// so loads of different uses are never merged and no momentum stays in a
+// register between uses (a sum is read again where it is needed).
+__device__ __forceinline__ int fresh_lane(int lane) {
+  asm volatile("" : "+v"(lane));
+  return lane;
+}
+template <unsigned MASK, unsigned INMASK, int NEXT, int BLOCK>
+__device__ __forceinline__ void flow_momentum_lds(double out[4], const double* smom, int lane) {
+  const int l = fresh_lane(lane);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NEXT; ++i)
+      if (MASK & (1u << i)) {
+        const double x = smom[(i * 4 + mu) * BLOCK + l];
+        acc = (INMASK & (1u << i)) ? acc + x : acc - x;
+      }
+    out[mu] = acc;
+  }
+}
+template <int BLOCK>
+__device__ __forceinline__ void load_mom_lds(double out[4], const double* smom, int lane, int i) {
+  const int l = fresh_lane(lane);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) out[mu] = smom[(i * 4 + mu) * BLOCK + l];
+}
+
 template <typename T> __device__ __forceinline__ void to_t(T out[4], const double in[4]) {
   out[0] = (T)in[0]; out[1] = (T)in[1]; out[2] = (T)in[2]; out[3] = (T)in[3];
 }
 
-// 1 / (P^2 - m^2) in double precision.
+// 1 / (P^2 - m^2) in double precision: the hardware reciprocal refined by
+// two Newton-Raphson steps y <- y + y (1 - x y), within an ulp or two of the
+// correctly rounded quotient for the normal-range denominators of these
+// propagators (the IEEE division sequence takes twice the instructions).
 __device__ __forceinline__ double inv_virt(const double P[4], double m) {
-  return 1.0 / (P[0] * P[0] - P[1] * P[1] - P[2] * P[2] - P[3] * P[3] - m * m);
+  const double x = P[0] * P[0] - P[1] * P[1] - P[2] * P[2] - P[3] * P[3] - m * m;
+  double y = __builtin_amdgcn_rcp(x);
+  double r = __builtin_fma(-x, y, 1.0);
+  y = __builtin_fma(y, r, y);
+  r = __builtin_fma(-x, y, 1.0);
+  return __builtin_fma(y, r, y);
 }
 
 }  // namespace mgme
