@@ -85,13 +85,14 @@ class GGBody:
     amplitude needs (computed at first use), and the amplitude values."""
 
     def __init__(self, sched: Schedule, pdg: List[int], em: Emitter, fresh_externals: bool = True,
-                 lds_momenta: bool = False):
+                 lds_momenta: bool = False, inplace: bool = None):
         """lds_momenta: the momenta are read from the lane's LDS rows (fused
         kernels) instead of the register array q (one lane per event and
         helicity in the staged kernels)."""
         self.sched = sched
         self.em = em
         self.lds = lds_momenta
+        self.inplace = lds_momenta if inplace is None else inplace
         n_ext = len(pdg)
         incoming = [i < 2 for i in range(n_ext)]
         q_leg = pdg.index(6)
@@ -120,14 +121,14 @@ class GGBody:
 
     def fr(self, v: str) -> str:
         fn = self.fresh_fn.get(v, "fresh")
-        if self.lds:
+        if self.inplace:
             return v  # laundered in place by prep()
         return f"{fn}({v})" if fn else v
 
     def prep(self, names) -> str:
         """Statements giving the inputs of the next routine call new
         identities in place (fused kernels); empty otherwise."""
-        if not self.lds:
+        if not self.inplace:
             return ""
         out = []
         for v in dict.fromkeys(names):
@@ -241,7 +242,8 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
                     colour="\n".join(colour))
 
 
-def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefetch: int = 6) -> Dict:
+def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefetch: int = 6,
+                   inplace: bool = False) -> Dict:
     """g g -> t t~ + n g, staged for processes whose colour-flow vector does
     not fit in registers.  The amplitude vertices, in low-register-pressure
     order, are split into `n_chunks` kernels.  Each kernel keeps at most
@@ -270,7 +272,7 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
         # External wavefunctions are used without fresh copies here: with them
         # the double-precision chunk kernels spill far more and returned wrong
         # results on gfx950 (cause not isolated); without them they pass parity.
-        body = GGBody(sched, pdg, em, fresh_externals=False)
+        body = GGBody(sched, pdg, em, fresh_externals=False, inplace=inplace)
         uses: Dict[int, List[int]] = {}
         for j, a in enumerate(chunk):
             for f, _, _ in a.coeffs:
@@ -463,11 +465,19 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
 """
 
 LAUNCH_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: launcher.
+// The kernel instantiations of each precision sit in units of their own
+// (me_{name}_<precision>.hip) so that they compile in parallel.
 #include "me_{name}_kernel.h"
 
 extern "C" hipError_t mgme_select_{name}(int prec, const double* mom, long long nevt, long long ld,
                                           const mgme::MeArgs* args, double* out, const mgme::SelectArgs* sel,
                                           hipStream_t stream);
+extern "C" hipError_t mgme_run_{name}_d(int per_hel, dim3 grid, const double* mom, long long nevt, long long ld,
+                                         const mgme::MeArgs* args, double* out, long long ldo, hipStream_t stream);
+extern "C" hipError_t mgme_run_{name}_f(int per_hel, dim3 grid, const double* mom, long long nevt, long long ld,
+                                         const mgme::MeArgs* args, double* out, long long ldo, hipStream_t stream);
+extern "C" hipError_t mgme_run_{name}_dc(int per_hel, dim3 grid, const double* mom, long long nevt, long long ld,
+                                          const mgme::MeArgs* args, double* out, long long ldo, hipStream_t stream);
 
 extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                           const mgme::MeArgs* args, double* out, long long ldo,
@@ -506,18 +516,24 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
     return err != hipSuccess ? err : ferr;
   }}
   const dim3 grid((unsigned)((nevt + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
-  if (prec == 0) {{
-    if (per_hel) me_kernel<double, 1><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
-    else me_kernel<double, 0><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
-  }} else if (prec == 3) {{
-    // double-precision diagrams, single-precision colour algebra
-    if (per_hel)
-      me_kernel<double, 1, float><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
-    else me_kernel<double, 0, float><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
-  }} else {{
-    if (per_hel) me_kernel<float, 1><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
-    else me_kernel<float, 0><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
-  }}
+  if (prec == 0) return mgme_run_{name}_d(per_hel, grid, mom, nevt, ld, args, out, ldo, stream);
+  if (prec == 3) return mgme_run_{name}_dc(per_hel, grid, mom, nevt, ld, args, out, ldo, stream);
+  return mgme_run_{name}_f(per_hel, grid, mom, nevt, ld, args, out, ldo, stream);
+}}
+"""
+
+RUN_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: {what}.
+#include "me_{name}_kernel.h"
+
+extern "C" hipError_t mgme_run_{name}_{tag}(int per_hel, dim3 grid, const double* mom, long long nevt, long long ld,
+                                             const mgme::MeArgs* args, double* out, long long ldo,
+                                             hipStream_t stream) {{
+  using namespace mgme::{name};
+  const dim3 block(MGME_ME_BLOCK);
+  if (per_hel)
+    me_kernel<{T}, 1, {TC}><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
+  else
+    me_kernel<{T}, 0, {TC}><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
   return hipGetLastError();
 }}
 """
@@ -564,9 +580,14 @@ def kernel_sources(meta: Dict) -> Dict[str, str]:
     """File name -> source for a process evaluated by one fused kernel."""
     title = " ".join(str(x) for x in meta["pdg"])
     name = meta["name"]
-    return {f"me_{name}_kernel.h": KERNEL_HEADER_TEMPLATE.format(title=title, **meta),
-            f"me_{name}.hip": LAUNCH_TEMPLATE.format(title=title, name=name),
-            f"me_{name}_sel.hip": SELECT_TEMPLATE.format(title=title, name=name)}
+    out = {f"me_{name}_kernel.h": KERNEL_HEADER_TEMPLATE.format(title=title, **meta),
+           f"me_{name}.hip": LAUNCH_TEMPLATE.format(title=title, name=name),
+           f"me_{name}_sel.hip": SELECT_TEMPLATE.format(title=title, name=name)}
+    for tag, T, TC, what in (("d", "double", "double", "FP64 diagrams and colour sum"),
+                             ("f", "float", "double", "FP32 diagrams, FP64 colour sum"),
+                             ("dc", "double", "float", "FP64 diagrams, FP32 colour algebra")):
+        out[f"me_{name}_{tag}.hip"] = RUN_TEMPLATE.format(title=title, name=name, tag=tag, T=T, TC=TC, what=what)
+    return out
 
 
 CHUNK_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: diagram chunk {chunk} of {n_chunks}.
