@@ -124,7 +124,11 @@ int mgme_rambo(const mgme_process* proc, double sqrt_s, unsigned long long seed,
  * Processes with many colour flows (g g -> t t~ g g g), and MGME_MIXED for
  * every process, stage colour-flow amplitudes in a workspace taken from the
  * stream-ordered allocator (hipMallocAsync) and returned at the end of the
- * call (at most a few GB, on `hip_stream`).
+ * call (at most a few GB, on `hip_stream`).  A batch too small to give every
+ * SIMD several waves spreads its helicities, in groups of 8, over more lanes
+ * and takes 8 bytes per group and event for the partial sums; the group sums
+ * are added in the same order whatever the batch size, so an event's |M|^2
+ * does not depend on the batch it is in.
  * Errors: EINVAL, EDEVICE (also when the workspace cannot be allocated). */
 int mgme_matrix_element(const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
                         int precision, double* d_me, void* hip_stream);

@@ -85,7 +85,8 @@ class GGBody:
     amplitude needs (computed at first use), and the amplitude values."""
 
     def __init__(self, sched: Schedule, pdg: List[int], em: Emitter, fresh_externals: bool = True,
-                 lds_momenta: bool = False, inplace: bool = None):
+                 lds_momenta: bool = False, inplace: bool = None, mom_block: str = "MGME_ME_BLOCK",
+                 ext_lds: bool = False):
         """lds_momenta: the momenta are read from the lane's LDS rows (fused
         kernels) instead of the register array q (one lane per event and
         helicity in the staged kernels)."""
@@ -93,6 +94,10 @@ class GGBody:
         self.em = em
         self.lds = lds_momenta
         self.inplace = lds_momenta if inplace is None else inplace
+        self.mom_block = mom_block
+        self.ext_lds = ext_lds
+        self.gluon = [x == 21 for x in pdg]
+        self.nload = 0
         n_ext = len(pdg)
         incoming = [i < 2 for i in range(n_ext)]
         q_leg = pdg.index(6)
@@ -101,18 +106,21 @@ class GGBody:
         for i in range(n_ext):
             lam = f"((hc >> {n_ext - 1 - i}) & 1 ? 1 : -1)"
             if self.lds:
-                em.w(f"double q{i}[4]; load_mom_lds<MGME_ME_BLOCK>(q{i}, smom, lane, {i});")
+                em.w(f"double q{i}[4]; load_mom_lds<{mom_block}>(q{i}, smom, lane, {i});")
                 qi = f"q{i}"
             else:
                 qi = f"q[{i}]"
-            cq = "" if self.lds else "const "
             if pdg[i] == 21:
-                em.w(f"{cq}wf<T> x{i} = ext_vec<T>({qi}, {lam}, {'false' if incoming[i] else 'true'});")
+                ext = f"ext_vec<T>({qi}, {lam}, {'false' if incoming[i] else 'true'})"
                 self.fresh_fn[f"x{i}"] = "fresh_pol"
             elif i == q_leg:
-                em.w(f"{cq}wf<T> x{i} = ext_bra<T>({qi}, mt, {lam}, false);")
+                ext = f"ext_bra<T>({qi}, mt, {lam}, false)"
             else:
-                em.w(f"{cq}wf<T> x{i} = ext_ket<T>({qi}, mt, {lam}, true);")
+                ext = f"ext_ket<T>({qi}, mt, {lam}, true)"
+            if self.ext_lds:
+                em.w(f"store_wf_lds<T, 256>(sext, {i}, xl, {ext});")
+            else:
+                em.w(f"{'' if self.lds else 'const '}wf<T> x{i} = {ext};")
             self.names[("X", i)] = f"x{i}"
             if not fresh_externals:
                 self.fresh_fn[f"x{i}"] = ""
@@ -127,11 +135,14 @@ class GGBody:
 
     def prep(self, names) -> str:
         """Statements giving the inputs of the next routine call new
-        identities in place (fused kernels); empty otherwise."""
-        if not self.inplace:
-            return ""
+        identities in place (fused kernels); empty otherwise.  With the
+        external wavefunctions in LDS, also their loads (see use())."""
         out = []
         for v in dict.fromkeys(names):
+            if v.startswith("u"):
+                continue
+            if not self.inplace:
+                continue
             fn = self.fresh_fn.get(v, "fresh")
             if fn == "fresh":
                 out.append(f"launder({v});")
@@ -142,7 +153,7 @@ class GGBody:
     def fm(self, out: str, mask: int) -> str:
         """Statement computing the flow-in momentum of the legs in `mask`."""
         if self.lds:
-            return f"flow_momentum_lds<{mask}u, {self.inmask}u, NEXT, MGME_ME_BLOCK>({out}, smom, lane);"
+            return f"flow_momentum_lds<{mask}u, {self.inmask}u, NEXT, {self.mom_block}>({out}, smom, lane);"
         return f"flow_momentum<{mask}u, {self.inmask}u, NEXT>({out}, q);"
 
     def mom(self, var: str, mask: int) -> str:
@@ -152,6 +163,14 @@ class GGBody:
         return self.sched.currents[k].mask if k[0] != "X" else 1 << k[1]
 
     def need(self, key) -> str:
+        if key[0] == "X" and self.ext_lds:
+            # a fresh load of the external wavefunction for this use
+            i = key[1]
+            v = f"u{self.nload}"
+            self.nload += 1
+            fn = "load_pol_lds" if self.gluon[i] else "load_wf_lds"
+            self.em.w(f"const wf<T> {v} = {fn}<T, 256>(sext, {i}, xl);")
+            return v
         if key in self.names:
             return self.names[key]
         em, fr, mom = self.em, self.fr, self.mom
@@ -243,7 +262,7 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
 
 
 def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefetch: int = 6,
-                   inplace: bool = False) -> Dict:
+                   inplace: bool = False, lds: bool = False) -> Dict:
     """g g -> t t~ + n g, staged for processes whose colour-flow vector does
     not fit in registers.  The amplitude vertices, in low-register-pressure
     order, are split into `n_chunks` kernels.  Each kernel keeps at most
@@ -272,7 +291,8 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
         # External wavefunctions are used without fresh copies here: with them
         # the double-precision chunk kernels spill far more and returned wrong
         # results on gfx950 (cause not isolated); without them they pass parity.
-        body = GGBody(sched, pdg, em, fresh_externals=False, inplace=inplace)
+        body = GGBody(sched, pdg, em, fresh_externals=False, inplace=inplace, lds_momenta=lds, mom_block="64",
+                      ext_lds=lds)
         uses: Dict[int, List[int]] = {}
         for j, a in enumerate(chunk):
             for f, _, _ in a.coeffs:
@@ -340,7 +360,7 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
     overflow_of = [[s for s, f in enumerate(overflow_flow) if f == fl] for fl in range(ncol)]
     return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "",
                     staged=True, chunk_bodies=chunk_bodies, n_overflow=len(overflow_flow), n_rmw=n_rmw,
-                    flops_exec_per_hel=flops_exec,
+                    flops_exec_per_hel=flops_exec, lds=lds,
                     overflow_of=overflow_of, colour_num=[int(v * cden) for row in C for v in row])
 
 
@@ -430,8 +450,17 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) smom[(i * 4 + mu) * MGME_ME_BLOCK + lane] = mom[(long long)(i * 4 + mu) * ld + e];
   const double mt = args.mt;
+  // The good helicities are summed in groups of MGME_HEL_GROUP, the group
+  // sums in group order.  A lane takes groups blockIdx.y, blockIdx.y +
+  // gridDim.y, ...: all of them when gridDim.y == 1; otherwise each group sum
+  // goes to aux[g*lda + e] and the helicity-sum kernel adds them in the same
+  // order, so every launch shape gives the same bits.
   double total = 0.0;
-  for (int ih = 0; ih < args.nhel; ++ih) {{
+  const int ngroup = (args.nhel + MGME_HEL_GROUP - 1) / MGME_HEL_GROUP;
+  for (int g = blockIdx.y; g < ngroup; g += gridDim.y) {{
+  double part = 0.0;
+  const int hend = args.nhel < (g + 1) * MGME_HEL_GROUP ? args.nhel : (g + 1) * MGME_HEL_GROUP;
+  for (int ih = g * MGME_HEL_GROUP; ih < hend; ++ih) {{
     const int hc = args.hel[ih];
 {body}
     if constexpr (MODE == 2) {{
@@ -443,7 +472,7 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
       if constexpr (MODE == 1) {{
         out[(long long)ih * ldo + e] = me * args.factor;
       }} else {{
-        total += me;
+        part += me;
         if constexpr (MODE == 3) {{
           aux[(long long)ih * lda + e] = me;
 #pragma unroll
@@ -453,7 +482,14 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
       }}
     }}
   }}
-  if constexpr (MODE == 0 || MODE == 3) out[e] = total * args.factor;
+  if constexpr (MODE == 0 || MODE == 3) {{
+    if (gridDim.y == 1) total += part;
+    else aux[(long long)g * lda + e] = part;
+  }}
+  }}
+  if constexpr (MODE == 0 || MODE == 3) {{
+    if (gridDim.y == 1) out[e] = total * args.factor;
+  }}
   if constexpr (MODE == 3) {{
 #pragma unroll
     for (int s = 0; s < NCOL; ++s) aux[(long long)(args.nhel + s) * lda + e] = j2[s * MGME_ME_BLOCK + threadIdx.x];
@@ -530,11 +566,26 @@ extern "C" hipError_t mgme_run_{name}_{tag}(int per_hel, dim3 grid, const double
                                              hipStream_t stream) {{
   using namespace mgme::{name};
   const dim3 block(MGME_ME_BLOCK);
-  if (per_hel)
+  if (per_hel) {{
     me_kernel<{T}, 1, {TC}><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
-  else
+    return hipGetLastError();
+  }}
+  // a batch too small to fill the GPU spreads its helicity groups over grid.y
+  const int ngroup = (args->nhel + MGME_HEL_GROUP - 1) / MGME_HEL_GROUP;
+  const int split = mgme::helicity_split((long long)grid.x * (MGME_ME_BLOCK / 64), ngroup);
+  if (split <= 1) {{
     me_kernel<{T}, 0, {TC}><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
-  return hipGetLastError();
+    return hipGetLastError();
+  }}
+  double* part = nullptr;
+  hipError_t err = hipMallocAsync((void**)&part, sizeof(double) * (size_t)ngroup * (size_t)nevt, stream);
+  if (err != hipSuccess) return err;
+  me_kernel<{T}, 0, {TC}><<<dim3(grid.x, (unsigned)split), block, 0, stream>>>(mom, nevt, ld, *args, out, ldo,
+                                                                               nullptr, part, nevt);
+  err = hipGetLastError();
+  if (err == hipSuccess) err = mgme::launch_helicity_sum(nevt, ngroup, part, nevt, args->factor, out, stream);
+  const hipError_t ferr = hipFreeAsync(part, stream);
+  return err != hipSuccess ? err : ferr;
 }}
 """
 
@@ -611,14 +662,7 @@ __global__ void __launch_bounds__(256) chunk_kernel(const double* __restrict__ m
   // 64 consecutive events per wave, one helicity per wave (uniform)
   const int hs = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (threadIdx.x >> 6));
   const long long e = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
-  if (hs >= args.nhel || e >= nevt) return;
-  const int hc = args.hel[hs];
-  const double mt = args.mt;
-  double q[NEXT][4];
-#pragma unroll
-  for (int i = 0; i < NEXT; ++i)
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) q[i][mu] = mom[(long long)(i * 4 + mu) * ld + e];
+{prologue}
   cx<T>* __restrict__ Jc = Jbuf + (long long)hs * NCOL * ldp + e;
   cx<T>* __restrict__ Ov = Ovbuf + (long long)hs * NOV * ldp + e;
   (void)Ov;
@@ -780,15 +824,42 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
 """
 
 
+CHUNK_PROLOGUE_REGS = r"""  if (hs >= args.nhel || e >= nevt) return;
+  const int hc = args.hel[hs];
+  const double mt = args.mt;
+  double q[NEXT][4];
+#pragma unroll
+  for (int i = 0; i < NEXT; ++i)
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) q[i][mu] = mom[(long long)(i * 4 + mu) * ld + e];"""
+
+# The four waves of a block evaluate the same 64 events (one helicity each):
+# their momenta are staged once in LDS; each lane's external wavefunctions
+# are stored in LDS and loaded again at every use.
+CHUNK_PROLOGUE_LDS = r"""  const int lane = threadIdx.x & 63;  // event within the block
+  const int xl = threadIdx.x;         // lane within the block
+  __shared__ double smom[NEXT * 4 * 64];
+  __shared__ T sext[NEXT * 8 * 256];
+  for (int k = threadIdx.x; k < NEXT * 4 * 64; k += 256) {
+    const long long ev = (long long)blockIdx.x * 64 + (k & 63);
+    smom[k] = ev < nevt ? mom[(long long)(k >> 6) * ld + ev] : 0.0;
+  }
+  __syncthreads();
+  if (hs >= args.nhel || e >= nevt) return;
+  const int hc = args.hel[hs];
+  const double mt = args.mt;"""
+
+
 def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 16384, nb: int = 30) -> Dict[str, str]:
     """File name -> source for a staged process."""
     title = " ".join(str(x) for x in meta["pdg"])
     out = {}
     nchunk = len(meta["chunk_bodies"])
+    prologue = CHUNK_PROLOGUE_LDS if meta.get("lds") else CHUNK_PROLOGUE_REGS
     for c, body in enumerate(meta["chunk_bodies"]):
         out[f"me_{meta['name']}_chunk{c}.hip"] = CHUNK_TEMPLATE.format(
             title=title, chunk=c, n_chunks=nchunk, name=meta["name"], n_ext=meta["n_ext"],
-            ncol=meta["ncol"], n_overflow=max(1, meta["n_overflow"]), body=body)
+            ncol=meta["ncol"], n_overflow=max(1, meta["n_overflow"]), body=body, prologue=prologue)
     sums = []
     for fl, sl in enumerate(meta["overflow_of"]):
         if not sl:

@@ -448,6 +448,35 @@ __device__ __forceinline__ void load_mom_lds(double out[4], const double* smom, 
   for (int mu = 0; mu < 4; ++mu) out[mu] = smom[(i * 4 + mu) * BLOCK + l];
 }
 
+// External wavefunctions staged per lane in LDS: the eight real components
+// of leg i at s[(i*8 + k)*NL + lane].  Each use loads them again through a
+// laundered lane index, so none stays in registers between uses.
+template <typename T, int NL>
+__device__ __forceinline__ void store_wf_lds(T* s, int i, int lane, const wf<T>& w) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    s[(i * 8 + 2 * c) * NL + lane] = w.c[c].re;
+    s[(i * 8 + 2 * c + 1) * NL + lane] = w.c[c].im;
+  }
+}
+template <typename T, int NL> __device__ __forceinline__ wf<T> load_wf_lds(const T* s, int i, int lane) {
+  const int l = fresh_lane(lane);
+  wf<T> w;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) w.c[c] = mk<T>(s[(i * 8 + 2 * c) * NL + l], s[(i * 8 + 2 * c + 1) * NL + l]);
+  return w;
+}
+// A polarisation vector: time component zero, z component real.
+template <typename T, int NL> __device__ __forceinline__ wf<T> load_pol_lds(const T* s, int i, int lane) {
+  const int l = fresh_lane(lane);
+  wf<T> w;
+  w.c[0] = mk<T>((T)0, (T)0);
+  w.c[1] = mk<T>(s[(i * 8 + 2) * NL + l], s[(i * 8 + 3) * NL + l]);
+  w.c[2] = mk<T>(s[(i * 8 + 4) * NL + l], s[(i * 8 + 5) * NL + l]);
+  w.c[3] = mk<T>(s[(i * 8 + 6) * NL + l], (T)0);
+  return w;
+}
+
 template <typename T> __device__ __forceinline__ void to_t(T out[4], const double in[4]) {
   out[0] = (T)in[0]; out[1] = (T)in[1]; out[2] = (T)in[2]; out[3] = (T)in[3];
 }

@@ -8,6 +8,9 @@
 
 #define MGME_MAX_HEL 128
 
+// Good helicities per group of the helicity sum (see the generated kernels).
+#define MGME_HEL_GROUP 8
+
 namespace mgme {
 
 // Passed by value as a kernel argument, so that the helicity list is read
@@ -42,5 +45,10 @@ struct SelectArgs {
 using LaunchFn = hipError_t (*)(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                 const MeArgs* args, double* out, long long ldo, const SelectArgs* sel,
                                 hipStream_t stream);
+
+// Number of grid rows over which a fused kernel spreads its ngroup helicity
+// groups when `waves` waves of 64 events would leave the GPU underfilled
+// (fewer than four waves per SIMD); 1 for large batches.
+int helicity_split(long long waves, int ngroup);
 
 }  // namespace mgme

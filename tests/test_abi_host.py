@@ -90,3 +90,28 @@ def test_last_error_is_thread_local():
     t.start()
     t.join()
     assert main_msg != b"" and seen == [b""]
+
+
+def test_event_level_entry_points_reject_bad_arguments():
+    """mgme_select, mgme_event_weights and mgme_unweight validate their
+    arguments before any device call."""
+    import paper_2303_18244_amd as M
+
+    L = _lib()
+    EINVAL = M.MGME_EINVAL
+    assert L.mgme_select(None, None, 10, 10, 0, None, None, None, None, None, None) == EINVAL
+    stats = (ctypes.c_double * 3)()
+    buf = (ctypes.c_double * 16)()
+    assert L.mgme_event_weights(1500.0, buf, buf, -1, None, stats, None) == EINVAL
+    assert L.mgme_event_weights(1500.0, None, buf, 10, None, stats, None) == EINVAL
+    assert L.mgme_event_weights(1500.0, buf, buf, 10, None, None, None) == EINVAL
+    assert L.mgme_event_weights(0.0, buf, buf, 10, None, stats, None) == EINVAL
+    assert L.mgme_event_weights(float("nan"), buf, buf, 10, None, stats, None) == EINVAL
+    idx = (ctypes.c_longlong * 16)()
+    n = (ctypes.c_longlong * 1)()
+    assert L.mgme_unweight(buf, buf, -1, buf, idx, n, None) == EINVAL
+    assert L.mgme_unweight(buf, buf, 10, None, idx, n, None) == EINVAL
+    assert L.mgme_unweight(buf, None, 10, buf, idx, n, None) == EINVAL
+    assert L.mgme_unweight(buf, buf, 10, buf, None, n, None) == EINVAL
+    assert L.mgme_unweight(buf, buf, 10, buf, idx, None, None) == EINVAL
+    assert b"NULL" in L.mgme_last_error() or b"nevt" in L.mgme_last_error()
