@@ -673,15 +673,12 @@ __global__ void __launch_bounds__(256) chunk_kernel(const double* __restrict__ m
 }}  // namespace {name}
 }}  // namespace mgme
 
-extern "C" hipError_t mgme_{name}_chunk{chunk}(int prec, dim3 grid, const double* mom, long long nevt, long long ld,
-                                              const mgme::MeArgs* args, void* Jbuf, void* Ovbuf, long long ldp,
-                                              hipStream_t stream) {{
-  if (prec == 0)
-    mgme::{name}::c{chunk}::chunk_kernel<double><<<grid, 256, 0, stream>>>(mom, nevt, ld, *args,
-        (mgme::cx<double>*)Jbuf, (mgme::cx<double>*)Ovbuf, ldp);
-  else
-    mgme::{name}::c{chunk}::chunk_kernel<float><<<grid, 256, 0, stream>>>(mom, nevt, ld, *args,
-        (mgme::cx<float>*)Jbuf, (mgme::cx<float>*)Ovbuf, ldp);
+// {T} diagrams (each precision in a unit of its own, compiled in parallel)
+extern "C" hipError_t mgme_{name}_chunk{chunk}_{tag}(dim3 grid, const double* mom, long long nevt, long long ld,
+                                                    const mgme::MeArgs* args, void* Jbuf, void* Ovbuf, long long ldp,
+                                                    hipStream_t stream) {{
+  mgme::{name}::c{chunk}::chunk_kernel<{T}><<<grid, 256, 0, stream>>>(mom, nevt, ld, *args,
+      (mgme::cx<{T}>*)Jbuf, (mgme::cx<{T}>*)Ovbuf, ldp);
   return hipGetLastError();
 }}
 """
@@ -702,7 +699,9 @@ constexpr int NCOL = {ncol};
 constexpr long long NOV = {n_overflow};
 constexpr int NB = {nb};  // flows per block of the quadratic form
 
-// colour-matrix numerators (common denominator applied in the final factor)
+// colour-matrix numerators (common denominator applied in the final factor),
+// upper triangle of the symmetric matrix with the off-diagonal entries
+// doubled: Re(J^dagger C J) = sum_s Re(conj(J_s) sum_(t >= s) kC[s][t] J_t)
 __constant__ double kC[NCOL * NCOL] = {{{cnum}}};
 
 // Adds the overflow slots to J (fixed at generation), then
@@ -724,7 +723,7 @@ __global__ void __launch_bounds__(256) colour_kernel(long long nevt, const MeArg
     TC yr[NB], yi[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) yr[k] = yi[k] = (TC)0;
-    for (int t = 0; t < NCOL; ++t) {{
+    for (int t = b; t < NCOL; ++t) {{
       const cx<T> jt = J[(long long)t * ldp];
       const TC jr = (TC)jt.re, ji = (TC)jt.im;
 #pragma unroll
@@ -850,6 +849,12 @@ CHUNK_PROLOGUE_LDS = r"""  const int lane = threadIdx.x & 63;  // event within t
   const double mt = args.mt;"""
 
 
+def _upper_doubled(num: List[int], n: int) -> List[int]:
+    """Row-major n x n: 0 below the diagonal, the diagonal, twice the
+    off-diagonal entries above it (the matrix is symmetric)."""
+    return [0 if t < s else (num[s * n + t] if t == s else 2 * num[s * n + t]) for s in range(n) for t in range(n)]
+
+
 def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 16384, nb: int = 30) -> Dict[str, str]:
     """File name -> source for a staged process."""
     title = " ".join(str(x) for x in meta["pdg"])
@@ -857,9 +862,11 @@ def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 1
     nchunk = len(meta["chunk_bodies"])
     prologue = CHUNK_PROLOGUE_LDS if meta.get("lds") else CHUNK_PROLOGUE_REGS
     for c, body in enumerate(meta["chunk_bodies"]):
-        out[f"me_{meta['name']}_chunk{c}.hip"] = CHUNK_TEMPLATE.format(
-            title=title, chunk=c, n_chunks=nchunk, name=meta["name"], n_ext=meta["n_ext"],
-            ncol=meta["ncol"], n_overflow=max(1, meta["n_overflow"]), body=body, prologue=prologue)
+        for tag, T in (("d", "double"), ("f", "float")):
+            out[f"me_{meta['name']}_chunk{c}_{tag}.hip"] = CHUNK_TEMPLATE.format(
+                title=title, chunk=c, n_chunks=nchunk, name=meta["name"], n_ext=meta["n_ext"],
+                ncol=meta["ncol"], n_overflow=max(1, meta["n_overflow"]), body=body, prologue=prologue,
+                tag=tag, T=T)
     sums = []
     for fl, sl in enumerate(meta["overflow_of"]):
         if not sl:
@@ -869,15 +876,16 @@ def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 1
         sums.append(f"  {{ cx<T> v = J[{fl}ll * ldp]; v.re += {terms_re}; v.im += {terms_im}; "
                     f"J[{fl}ll * ldp] = v; }}")
     decls = "\n".join(
-        f'extern "C" hipError_t mgme_{meta["name"]}_chunk{c}(int, dim3, const double*, long long, long long, '
-        f'const mgme::MeArgs*, void*, void*, long long, hipStream_t);' for c in range(nchunk))
+        f'extern "C" hipError_t mgme_{meta["name"]}_chunk{c}_{tag}(dim3, const double*, long long, long long, '
+        f'const mgme::MeArgs*, void*, void*, long long, hipStream_t);' for c in range(nchunk) for tag in "df")
     calls = "\n".join(
-        f"    if (err == hipSuccess) err = mgme_{meta['name']}_chunk{c}(dprec, grid, mom + start, n, ld, args, "
-        f"Jbuf, Ovbuf, sub, stream);" for c in range(nchunk))
+        f"    if (err == hipSuccess) err = (dprec == 0 ? mgme_{meta['name']}_chunk{c}_d : mgme_{meta['name']}_chunk{c}_f)"
+        f"(grid, mom + start, n, ld, args, Jbuf, Ovbuf, sub, stream);" for c in range(nchunk))
     assert meta["ncol"] % nb == 0
     out[f"me_{meta['name']}.hip"] = COLOUR_TEMPLATE.format(
         title=title, name=meta["name"], n_diagrams=meta["n_diagrams"], n_terms=meta["n_terms"],
         ncol=meta["ncol"], n_chunks=nchunk, n_overflow=max(1, meta["n_overflow"]), n_rmw=meta["n_rmw"], nb=nb,
-        cnum=", ".join(f"{v}.0" for v in meta["colour_num"]), overflow_sums="\n".join(sums),
+        cnum=", ".join(f"{v}.0" for v in _upper_doubled(meta["colour_num"], meta["ncol"])),
+        overflow_sums="\n".join(sums),
         chunk_decls=decls, chunk_calls=calls, workspace_bytes=workspace_bytes, max_sub=max_sub)
     return out
