@@ -177,19 +177,11 @@ class Schedule:
         return frozenset(out)
 
     # --------------------------------------------------------------- ordering
-    def low_pressure_order(self) -> List[Amp]:
-        """Order of the amplitude vertices that keeps few currents alive:
-        repeatedly take the amplitude needing the fewest new currents net of
-        the currents whose last use it is (greedy list scheduling)."""
-        uses: Dict[tuple, int] = {k: 0 for k in self.currents}
-        for c in self.currents.values():
-            for i in c.inputs:
-                if i in uses:
-                    uses[i] += 1
-        for a in self.amps:
-            for i in a.inputs:
-                if i in uses:
-                    uses[i] += 1
+    def low_pressure_order(self, amps: Optional[List[Amp]] = None) -> List[Amp]:
+        """Order of the amplitude vertices (all of them, or the subset `amps`,
+        whose currents are then evaluated afresh) that keeps few currents
+        alive: repeatedly take the amplitude needing the fewest new currents
+        net of the currents whose last use it is (greedy list scheduling)."""
         emitted: set = set()
         live: set = set()
 
@@ -201,18 +193,33 @@ class Schedule:
                 out.append(k)
             return out
 
-        todo = list(range(len(self.amps)))
+        if amps is None:
+            amps = self.amps
+            keys = list(self.currents)
+        else:
+            keys = closure([i for a in amps for i in a.inputs], [])
+        uses: Dict[tuple, int] = {k: 0 for k in keys}
+        for k in keys:
+            for i in self.currents[k].inputs:
+                if i in uses:
+                    uses[i] += 1
+        for a in amps:
+            for i in a.inputs:
+                if i in uses:
+                    uses[i] += 1
+
+        todo = list(range(len(amps)))
         order: List[Amp] = []
         while todo:
             best = None
             for i in todo:
-                new = closure(self.amps[i].inputs, [])
+                new = closure(amps[i].inputs, [])
                 cnt: Dict[tuple, int] = {}
                 for k in new:
                     for j in self.currents[k].inputs:
                         if j in uses:
                             cnt[j] = cnt.get(j, 0) + 1
-                for j in self.amps[i].inputs:
+                for j in amps[i].inputs:
                     if j in uses:
                         cnt[j] = cnt.get(j, 0) + 1
                 freed = sum(1 for j, c in cnt.items() if j in live and uses[j] == c)
@@ -221,8 +228,8 @@ class Schedule:
                     best = (score, i)
             i = best[1]
             todo.remove(i)
-            order.append(self.amps[i])
-            for k in closure(self.amps[i].inputs, []):
+            order.append(amps[i])
+            for k in closure(amps[i].inputs, []):
                 emitted.add(k)
                 live.add(k)
                 for j in self.currents[k].inputs:
@@ -230,7 +237,7 @@ class Schedule:
                         uses[j] -= 1
                         if uses[j] == 0:
                             live.discard(j)
-            for j in self.amps[i].inputs:
+            for j in amps[i].inputs:
                 if j in uses:
                     uses[j] -= 1
                     if uses[j] == 0:
