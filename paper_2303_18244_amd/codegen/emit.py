@@ -304,6 +304,7 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
         ptr = {f: 0 for f in uses}
         open_acc: Dict[int, str] = {}
         folded_here: set = set()
+        last_fold: Dict[int, int] = {}     # flow -> index of its latest fold in this chunk
         fold_lines: List[int] = []          # line index of every fold in this chunk
         rmw: List[tuple] = []               # (fold number, flow, prefetch variable)
         nacc = [0]
@@ -311,7 +312,11 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
         def fold(f):
             v = open_acc.pop(f)
             nonlocal n_rmw
-            if f in folded_here:
+            k = len(fold_lines)
+            # a flow this kernel stored before is read back like one from an
+            # earlier kernel, provided its prefetch (issued `prefetch` folds
+            # ahead) comes after that store; otherwise it goes to an overflow slot
+            if f in folded_here and not (k >= prefetch and last_fold[f] <= k - prefetch):
                 em.w(f"Ov[{len(overflow_flow)}ll * ldp] = {v};")
                 overflow_flow.append(f)
             elif f not in written:
@@ -323,6 +328,7 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
                 em.w(f"Jc[{f}ll * ldp] = {pf} + {v};")
                 n_rmw += 1
             folded_here.add(f)
+            last_fold[f] = k
             fold_lines.append(len(em.lines) - 1)
 
         for j, a in enumerate(chunk):
