@@ -544,10 +544,15 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
     float2* J = (float2*)ws;
     double* meh = (double*)(ws + (size_t)nh * NCOL * sizeof(float2) * sub);
     double* jamp2 = meh + (size_t)nh * sub;
+    const int ngroup = (nh + MGME_HEL_GROUP - 1) / MGME_HEL_GROUP;
     for (long long start = 0; start < nevt && err == hipSuccess; start += sub) {{
       const long long n = (nevt - start < sub) ? nevt - start : sub;
-      const dim3 grid((unsigned)((n + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
-      me_kernel<float, 2><<<grid, block, 0, stream>>>(mom + start, n, ld, *args, nullptr, sub, J, nullptr, 0);
+      const unsigned gx = (unsigned)((n + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK);
+      // each helicity's J is written on its own: a small batch spreads the
+      // helicity groups over grid rows
+      const int split = mgme::helicity_split((long long)gx * (MGME_ME_BLOCK / 64), ngroup);
+      me_kernel<float, 2><<<dim3(gx, (unsigned)split), block, 0, stream>>>(mom + start, n, ld, *args, nullptr, sub, J,
+                                                                            nullptr, 0);
       err = hipGetLastError();
       if (err == hipSuccess)
         err = mgme::launch_colour_mfma(n, nh, NCOL, J, sub, args->cfrag, per_hel ? out + start : meh,
@@ -576,12 +581,15 @@ extern "C" hipError_t mgme_run_{name}_{tag}(int per_hel, dim3 grid, const double
                                              hipStream_t stream) {{
   using namespace mgme::{name};
   const dim3 block(MGME_ME_BLOCK);
-  if (per_hel) {{
-    me_kernel<{T}, 1, {TC}><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
-    return hipGetLastError();
-  }}
   // a batch too small to fill the GPU spreads its helicity groups over grid.y
   const int ngroup = (args->nhel + MGME_HEL_GROUP - 1) / MGME_HEL_GROUP;
+  if (per_hel) {{
+    // each helicity's value is written on its own
+    const int hsplit = mgme::helicity_split((long long)grid.x * (MGME_ME_BLOCK / 64), ngroup);
+    me_kernel<{T}, 1, {TC}><<<dim3(grid.x, (unsigned)hsplit), block, 0, stream>>>(mom, nevt, ld, *args, out, ldo,
+                                                                                   nullptr, nullptr, 0);
+    return hipGetLastError();
+  }}
   const int split = mgme::helicity_split((long long)grid.x * (MGME_ME_BLOCK / 64), ngroup);
   if (split <= 1) {{
     me_kernel<{T}, 0, {TC}><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
