@@ -71,6 +71,7 @@ def lib():
                                 ctypes.c_int, dp]
         L.oracle_me_hel.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
         L.oracle_gauge.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
+        L.oracle_flows.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
         L.oracle_event_weights.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, dp, dp]
         L.oracle_unweight.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, ctypes.POINTER(ctypes.c_int64)]
         L.oracle_unweight.restype = ctypes.c_int64
@@ -203,6 +204,14 @@ class Process:
         out = np.zeros(self.n_hel)
         lib().oracle_me_hel(self._h, _dp(mom1), precision, _dp(out))
         return out
+
+    def flows(self, mom1: np.ndarray, hel: int) -> np.ndarray:
+        """Colour-ordered amplitudes of one helicity (basis order)."""
+        mom1 = np.ascontiguousarray(mom1, dtype=np.float64)
+        out = np.zeros(2 * self.n_colour)
+        if lib().oracle_flows(self._h, _dp(mom1), hel, _dp(out)) != 0:
+            raise ValueError("bad helicity")
+        return out[0::2] + 1j * out[1::2]
 
     def select(self, mom1: np.ndarray, r_hel: float, r_col: float):
         """(helicity code, colour flow, margins) for one event."""

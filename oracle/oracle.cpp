@@ -155,6 +155,20 @@ int oracle_gauge(void* proc, const double* mom, int leg, double out[2]) {
   return 0;
 }
 
+int oracle_flows(void* proc, const double* mom, int hel, double* J) {
+  auto* P = static_cast<oracle::Process*>(proc);
+  if (hel < 0 || hel >= P->n_hel) return -1;
+  const auto ev = P->make_event<double>(mom);
+  std::vector<std::complex<double>> amp, flows;
+  P->term_amplitudes(ev, hel, -1, amp);
+  P->flows(amp, flows);
+  for (int s = 0; s < P->ncol; ++s) {
+    J[2 * s] = flows[s].real();
+    J[2 * s + 1] = flows[s].imag();
+  }
+  return 0;
+}
+
 int oracle_event_weights(int64_t nevt, const double* wgt, const double* me, double sqrt_s, double* w,
                          double stats[3]) {
   if (nevt < 0 || !(sqrt_s > 0)) return -1;

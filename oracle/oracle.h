@@ -55,6 +55,11 @@ int oracle_me_hel(void* proc, const double* mom, int precision, double* me_hel);
  * out[1] = the same maximum without it. */
 int oracle_gauge(void* proc, const double* mom, int leg, double out[2]);
 
+/* Colour-ordered amplitudes J_s (n_colour complex values, re/im
+ * interleaved, basis order of oracle_colour_matrix) of helicity `hel` for
+ * one event: i times the colour-stripped amplitude, couplings included,
+ * before the averaging and symmetry factor. */
+int oracle_flows(void* proc, const double* mom, int hel, double* J);
 /* Cross-section weights w[e] = (wgt[e] * me[e]) * (0.3893793721e9 / (2 s)) in
  * pb for massless colliding partons, and stats = (sum w, sum w^2, max w). */
 int oracle_event_weights(int64_t nevt, const double* wgt, const double* me, double sqrt_s, double* w,

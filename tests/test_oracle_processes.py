@@ -3,7 +3,8 @@
 e+e- -> mu+mu- (s-channel photon + Z) and g g -> t t~ against per-event closed
 forms and total cross sections; g g -> t t~ + 1..3 gluons against gauge
 invariance, Lorentz invariance, Bose symmetry, the brute-force colour sum,
-the diagram and colour-flow counts and the published colour matrices.
+the diagram and colour-flow counts, the published colour matrices and the
+soft-gluon limit of the colour-ordered amplitudes.
 """
 import math
 import os
@@ -289,3 +290,92 @@ def test_unsupported_process(oracle_mod):
         oracle_mod.Process([21, 21, 5, -5])
     with pytest.raises(ValueError):
         oracle_mod.Process([21, 21, 6, -6], wt=1.5)
+
+
+# --------------------------------------------------------------- soft-gluon limit
+def _boost_to(p, beta_vec):
+    b2 = beta_vec @ beta_vec
+    g = 1.0 / math.sqrt(1.0 - b2)
+    bp = beta_vec @ p[1:]
+    out = np.empty(4)
+    out[0] = g * (p[0] + bp)
+    out[1:] = p[1:] + ((g - 1) * bp / b2 + g * p[0]) * beta_vec
+    return out
+
+
+def _recoil(final, masses, P_target):
+    """Final-state momenta (given in the frame where they sum to (M, 0)) mapped
+    onto total momentum P_target: three-momenta rescaled by a common factor so
+    that the energies sum to the new invariant mass, then boosted."""
+    M_new = math.sqrt(mdot(P_target, P_target))
+    p2 = np.sum(final[:, 1:] ** 2, axis=1)
+    lo, hi = 0.0, 1.0
+    for _ in range(200):
+        lam = 0.5 * (lo + hi)
+        if np.sum(np.sqrt(masses ** 2 + lam * lam * p2)) > M_new:
+            hi = lam
+        else:
+            lo = lam
+    q = np.concatenate([np.sqrt(masses ** 2 + lam * lam * p2)[:, None], lam * final[:, 1:]], axis=1)
+    return np.array([_boost_to(x, P_target[1:] / P_target[0]) for x in q])
+
+
+@pytest.mark.parametrize("hard_name,soft_leg,delta,tol,n_hel", [
+    ("gg_tt", 4, 1e-7, 1e-5, None),
+    ("gg_ttg", 5, 1e-7, 1e-5, None),
+    ("gg_ttgg", 6, 1e-6, 2e-3, 12),
+    ("gg_ttgg", 4, 1e-6, 2e-3, 6),
+])
+def test_soft_gluon_limit(procs, oracle_mod, hard_name, soft_leg, delta, tol, n_hel):
+    """Soft-gluon factorisation of the colour-ordered amplitudes: when the
+    energy of a final-state gluon k goes to zero, the flow (T^a1 ... T^am)_ij
+    whose ordering has k between neighbours a and b (the top quark before the
+    first gluon, the antitop after the last) tends to -g_s (eps*.p_a/k.p_a -
+    eps*.p_b/k.p_b) times the flow of the process without k, in the same order,
+    for every helicity (eikonal quark and gluon vertices, whose i g_s times the
+    propagator's i gives -g_s).  This ties each process with one more gluon,
+    g g -> t t~ g g g included, to the one below it, and so down to the g g ->
+    t t~ closed form; the deviation is O(k / sqrt(s))."""
+    names = list(oracle_mod.PROCESSES)
+    soft_name = names[names.index(hard_name) + 1]
+    H, S = procs[hard_name], procs[soft_name]
+    n = S.n_ext
+    sqrt_s = 1500.0
+    hard_ev, _ = events(oracle_mod, hard_name, 1, first=5)
+    hard_ev = hard_ev[0]
+    rng = np.random.default_rng(17)
+    u = rng.normal(size=3)
+    k = delta * sqrt_s * np.concatenate([[1.0], u / np.linalg.norm(u)])
+    masses = np.array([MT, MT] + [0.0] * (H.n_ext - 4))
+    final = _recoil(hard_ev[2:], masses, hard_ev[0] + hard_ev[1] - k)
+    hard_legs = [leg for leg in range(n) if leg != soft_leg]  # hard leg i is soft-event leg hard_legs[i]
+    mom = np.zeros((n, 4))
+    mom[soft_leg] = k
+    mom[hard_legs] = np.concatenate([hard_ev[:2], final])
+    basis_s = [tuple(b) for b in S.colour_matrix()[2].tolist()]
+    index_h = {tuple(b): i for i, b in enumerate(H.colour_matrix()[2].tolist())}
+    gs = math.sqrt(4 * math.pi * 0.118)
+    flows_h = [H.flows(hard_ev, h) for h in range(H.n_hel)]
+    scale = max(np.max(np.abs(J)) for J in flows_h)
+    hels = [h for h in range(H.n_hel) if np.max(np.abs(flows_h[h])) > 1e-8 * scale]
+    if n_hel is not None:
+        hels = list(rng.choice(hels, n_hel, replace=False))
+    checked = 0
+    for h in hels:
+        for lam in (-1, 1):
+            code = (1 << (n - 1 - soft_leg)) if lam > 0 else 0
+            for i, leg in enumerate(hard_legs):
+                if (h >> (H.n_ext - 1 - i)) & 1:
+                    code |= 1 << (n - 1 - leg)
+            J = S.flows(mom, code)
+            eps = np.conj(oracle_mod.external("eps", k, 0.0, lam))
+            for s, order in enumerate(basis_s):
+                j = order.index(soft_leg)
+                a = 2 if j == 0 else order[j - 1]
+                b = 3 if j == len(order) - 1 else order[j + 1]
+                eik = mdot(eps, mom[a]) / mdot(k, mom[a]) - mdot(eps, mom[b]) / mdot(k, mom[b])
+                hard_order = tuple(hard_legs.index(x) for x in order if x != soft_leg)
+                pred = -gs * eik * flows_h[h][index_h[hard_order]]
+                assert abs(J[s] - pred) <= tol * abs(eik) * scale * gs, (h, lam, order, J[s], pred)
+                checked += 1
+    assert checked >= 2 * len(hels) * len(basis_s)
