@@ -7,7 +7,7 @@ from __future__ import annotations
 
 from fractions import Fraction
 from math import lcm
-from typing import Dict, List
+from typing import Dict, List, Optional, Tuple
 
 from . import colour as col
 from .diagrams import enumerate_terms
@@ -86,10 +86,21 @@ class GGBody:
 
     def __init__(self, sched: Schedule, pdg: List[int], em: Emitter, fresh_externals: bool = True,
                  lds_momenta: bool = False, inplace: bool = None, mom_block: str = "MGME_ME_BLOCK",
-                 ext_lds: bool = False):
+                 ext_lds: bool = False, prefetch: bool = False):
         """lds_momenta: the momenta are read from the lane's LDS rows (fused
         kernels) instead of the register array q (one lane per event and
-        helicity in the staged kernels)."""
+        helicity in the staged kernels).
+
+        prefetch: software-pipelines the momenta and propagator denominators.
+        Without it a call's LDS loads can only start after its own register
+        barriers, i.e. once the previous call has finished, and with one wave
+        per SIMD nothing hides their latency.  With it, the loads of each
+        routine call are issued pf_dist calls earlier, right after that
+        call's barriers and ahead of a scheduling barrier (FP64 only) that
+        keeps the compiler from sinking them to their use; the momentum sums
+        and 1/(P^2 - m^2) follow in the block of the call just before, where
+        they overlap its arithmetic.  Call finish() once the body is
+        complete."""
         self.sched = sched
         self.em = em
         self.lds = lds_momenta
@@ -126,6 +137,138 @@ class GGBody:
                 self.fresh_fn[f"x{i}"] = ""
         self.inmask = sum(1 << i for i in range(n_ext) if incoming[i])
         self.counter = 0
+        self.prefetch = prefetch
+        self.pf_dist = 1
+        self.calls: List[Optional[tuple]] = []  # per routine call: its momentum needs
+        if prefetch:
+            em.w("@@PFHEAD@@")
+
+    def open_call(self, needs: Optional[tuple]) -> Tuple[int, str]:
+        """Registers a routine call with its momentum needs; returns its index
+        and the marker that finish() replaces with the prefetch of the next
+        call (empty without prefetching)."""
+        i = len(self.calls)
+        self.calls.append(needs)
+        if not self.prefetch:
+            return i, ""
+        self.em.w(f"@@PFDECL{i}@@")
+        return i, f"@@PF{i}@@"
+
+    def pf_decl(self, j: int) -> str:
+        needs = self.calls[j] if j < len(self.calls) else None
+        if needs is None:
+            return ""
+        kind = needs[0]
+        vecs = {"vvv": ["k1", "k2"], "prop": ["P"], "den": [], "amp3": ["k1", "k2", "k3"]}[kind]
+        parts = [f"T pf{j}_{v}[4];" for v in vecs]
+        if kind != "amp3":
+            parts.append(f"T pf{j}_den;")
+        return " ".join(parts)
+
+    def pf_code(self, j: int) -> str:
+        needs = self.calls[j] if j < len(self.calls) else None
+        return "" if needs is None else self.pf_code_split(j, needs)
+
+    def _union(self, j: int) -> int:
+        needs = self.calls[j] if j < len(self.calls) else None
+        u = 0
+        if needs is not None:
+            for m in needs[1:]:
+                if isinstance(m, int):
+                    u |= m
+        return u
+
+    def pf_loads(self, j: int) -> str:
+        """Distance 2: the LDS loads of call j into its raw registers."""
+        u = self._union(j)
+        if not u:
+            return ""
+        return f"load_legs_lds<{u}u, NEXT, {self.mom_block}>(pf{j}_r, smom, lane); pf_barrier<T>(); "
+
+    def pf_sums(self, j: int) -> str:
+        """Distance 2: sums and denominator of call j from its raw registers."""
+        needs = self.calls[j] if j < len(self.calls) else None
+        if needs is None:
+            return ""
+        return "{ " + self.pf_arith(j, needs, f"pf{j}_r")
+
+    def pf_code_split(self, j: int, needs: tuple) -> str:
+        """Distance 1: prefetch whose LDS loads sit above a scheduling barrier
+        (so the scheduler cannot sink them to their use) and whose arithmetic
+        sits below it."""
+        head = (f"{{ double r[NEXT][4]; load_legs_lds<{self._union(j)}u, NEXT, {self.mom_block}>(r, smom, lane); "
+                "pf_barrier<T>(); ")
+        return head + self.pf_arith(j, needs, "r")
+
+    def pf_arith(self, j: int, needs: tuple, r: str) -> str:
+        """Momentum sums and denominator of call j from the raw leg momenta in
+        register array `r`; closes the block the caller opened."""
+        kind, masks = needs[0], [m for m in needs[1:] if isinstance(m, int)]
+        I = self.inmask
+        if kind == "vvv":
+            m1, m2 = masks
+            body = (f"double k1d[4]; sum_legs<{m1}u, {I}u, NEXT>(k1d, {r}); double k2d[4]; sum_legs<{m2}u, {I}u, NEXT>(k2d, {r}); "
+                    f"to_t(pf{j}_k1, k1d); to_t(pf{j}_k2, k2d); "
+                    "const double Pd[4] = {k1d[0] + k2d[0], k1d[1] + k2d[1], k1d[2] + k2d[2], k1d[3] + k2d[3]}; "
+                    f"pf{j}_den = (T)inv_virt(Pd, 0.0); }} ")
+        elif kind == "prop":
+            body = (f"double Pd[4]; sum_legs<{masks[0]}u, {I}u, NEXT>(Pd, {r}); to_t(pf{j}_P, Pd); "
+                    f"pf{j}_den = (T)inv_virt(Pd, {needs[2]}); }} ")
+        elif kind == "den":
+            body = f"double Pd[4]; sum_legs<{masks[0]}u, {I}u, NEXT>(Pd, {r}); pf{j}_den = (T)inv_virt(Pd, 0.0); }} "
+        else:
+            body = " ".join(f"{{ double kd[4]; sum_legs<{m}u, {I}u, NEXT>(kd, {r}); to_t(pf{j}_{k}, kd); }}"
+                            for k, m in zip(("k1", "k2", "k3"), masks)) + " } "
+        return body
+
+    def finish(self) -> None:
+        """Fills the prefetch markers: block i issues the loads of call i+1;
+        the first call's are issued before any block."""
+        if not self.prefetch:
+            return
+        n = len(self.calls)
+        out = []
+        if self.pf_dist == 2:
+            for ln in self.em.lines:
+                t = ln.strip()
+                if t == "@@PFHEAD@@":
+                    decl = [f"double pf{j}_r[NEXT][4];" for j in (0, 1) if self._union(j)]
+                    decl += [self.pf_decl(0)]
+                    out.append("    " + " ".join(d for d in decl if d) + " " + self.pf_loads(0) + self.pf_loads(1)
+                               + self.pf_sums(0).rstrip())
+                    continue
+                if t.startswith("@@PFDECL"):
+                    i = int(t[len("@@PFDECL"):-2])
+                    d = self.pf_decl(i + 1)
+                    if self._union(i + 2):
+                        d = (d + " " if d else "") + f"double pf{i + 2}_r[NEXT][4];"
+                    if d:
+                        out.append("    " + d)
+                    continue
+                if "@@PF" in ln:
+                    i = int(ln.split("@@PF", 1)[1].split("@@", 1)[0])
+                    ln = ln.replace(f"@@PF{i}@@", self.pf_loads(i + 2) + self.pf_sums(i + 1))
+                out.append(ln)
+            self.em.lines = out
+            return
+        for ln in self.em.lines:
+            t = ln.strip()
+            if t == "@@PFHEAD@@":
+                d = self.pf_decl(0)
+                if d:
+                    out.append("    " + d + " " + self.pf_code(0).rstrip())
+                continue
+            if t.startswith("@@PFDECL"):
+                i = int(t[len("@@PFDECL"):-2])
+                d = self.pf_decl(i + 1)
+                if d:
+                    out.append("    " + d)
+                continue
+            if "@@PF" in ln:
+                i = int(ln.split("@@PF", 1)[1].split("@@", 1)[0])
+                ln = ln.replace(f"@@PF{i}@@", self.pf_code(i + 1) if i + 1 < n else "")
+            out.append(ln)
+        self.em.lines = out
 
     def fr(self, v: str) -> str:
         fn = self.fresh_fn.get(v, "fresh")
@@ -180,6 +323,10 @@ class GGBody:
         self.counter += 1
         em.w(f"wf<T> {v};")
         pre = self.prep(ins)
+        if self.prefetch:
+            self.emit_current_pf(cur, ins, v, pre)
+            self.names[key] = v
+            return v
         if cur.routine == "vvv_vec":
             c1, c2 = cur.tree.children
             em.w(f"{{ {pre}{mom('k1', c1.mask)} {mom('k2', c2.mask)}")
@@ -200,11 +347,45 @@ class GGBody:
         self.names[key] = v
         return v
 
+    def emit_current_pf(self, cur, ins, v, pre) -> None:
+        """A current whose momenta and denominator were prefetched."""
+        em, fr = self.em, self.fr
+        r = cur.routine
+        if r == "vvv_vec":
+            c1, c2 = cur.tree.children
+            j, pf = self.open_call(("vvv", c1.mask, c2.mask))
+            em.w(f"{{ {pre}{pf}")
+            em.w(f"  {v} = vvv_vec<T>({fr(ins[0])}, pf{j}_k1, {fr(ins[1])}, pf{j}_k2, pf{j}_den); }}")
+        elif r == "vvvv_vec":
+            j, pf = self.open_call(("den", cur.mask))
+            em.w(f"{{ {pre}{pf}")
+            em.w(f"  {v} = vvvv_vec<T, {cur.tree.s}>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])}, pf{j}_den); }}")
+        elif r in ("ket_prop", "bra_prop"):
+            j, pf = self.open_call(("prop", cur.mask, "mt"))
+            em.w(f"{{ {pre}{pf}")
+            em.w(f"  {v} = {r}<T>({fr(ins[0])}, {fr(ins[1])}, pf{j}_P, (T)mt, pf{j}_den); }}")
+        elif r == "ffv_vec":
+            j, pf = self.open_call(("den", cur.mask))
+            em.w(f"{{ {pre}{pf}")
+            em.w(f"  {v} = ffv_vec<T>({fr(ins[0])}, {fr(ins[1])}, pf{j}_den); }}")
+        else:
+            raise ValueError(r)
+
     def amplitude(self, a) -> None:
         """Opens a block defining `a`, the amplitude value; the caller closes it."""
         em, fr = self.em, self.fr
         ins = [self.need(k) for k in a.inputs]
         pre = self.prep(ins)
+        if self.prefetch:
+            if a.routine == "vvv_amp":
+                m1, m2, m3 = (self.leg_mask(k) for k in a.inputs)
+                j, pf = self.open_call(("amp3", m1, m2, m3))
+                em.w(f"{{ {pre}{pf}")
+                em.w(f"  const cx<T> a = vvv_amp<T>({fr(ins[0])}, pf{j}_k1, {fr(ins[1])}, pf{j}_k2, "
+                     f"{fr(ins[2])}, pf{j}_k3);")
+                return
+            _, pf = self.open_call(None)
+            pre = pre + pf
         if a.routine == "ffv_amp":
             em.w(f"{{ {pre}const cx<T> a = ffv_amp<T>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])});")
         elif a.routine == "vvv_amp":
@@ -245,19 +426,36 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
     """g g -> t t~ + n g, fused: the colour-flow amplitudes J stay in
     registers and the colour sum runs in the same kernel."""
     n_ext, gluon_legs, terms, n_diag, flows, C, cden, sched = _gg_setup(pdg)
-    em = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
-    body = GGBody(sched, pdg, em, lds_momenta=True)
     ncol = len(flows)
-    em.w(f"cx<T> J[{ncol}];")
-    em.w(f"for (int s = 0; s < {ncol}; ++s) J[s] = mk<T>((T)0, (T)0);")
-    for a in sched.low_pressure_order():
-        body.amplitude(a)
-        upd = " ".join(f"acc(J[{f}], a, {re}, {im});" for f, re, im in a.coeffs)
-        em.w(f"  {upd} }}")
+    order = sched.low_pressure_order()
+
+    def helicity_body(dist: int) -> List[str]:
+        em = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
+        body = GGBody(sched, pdg, em, lds_momenta=True, prefetch=True)
+        body.pf_dist = dist
+        for a in order:
+            body.amplitude(a)
+            upd = " ".join(f"acc(J[{f}], a, {re}, {im});" for f, re, im in a.coeffs)
+            em.w(f"  {upd} }}")
+        body.finish()
+        return ["  " + ln for ln in em.lines]
+
+    # Two software-pipelined forms of the same arithmetic: momenta loaded two
+    # routine calls ahead (their latency hidden behind a whole call) or one
+    # call ahead (fewer live registers).  The first is faster wherever it
+    # keeps the kernel's occupancy; for the FP32 kernels of six or more legs
+    # that keep the colour-flow sums in registers, it would cost the second
+    # wave per SIMD.
+    lines = [f"    cx<T> J[{ncol}];", f"    for (int s = 0; s < {ncol}; ++s) J[s] = mk<T>((T)0, (T)0);"]
+    if n_ext <= 5:
+        lines += helicity_body(2)
+    else:
+        lines += (["    if constexpr (sizeof(T) == 8 || MODE == 2) {"] + helicity_body(2) + ["    } else {"]
+                  + helicity_body(1) + ["    }"])
     colour = (["      TC mc = (TC)0;"] + ["  " + ln for ln in colour_sum_lines(C, cden)]
               + ["      const double me = (double)mc;"])
     flops_hel = sched.flops_per_helicity() + 2 * ncol * ncol + 4 * ncol + 90 * n_ext
-    return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "\n".join(em.lines),
+    return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "\n".join(lines),
                     colour="\n".join(colour))
 
 

@@ -448,6 +448,39 @@ __device__ __forceinline__ void load_mom_lds(double out[4], const double* smom, 
   for (int mu = 0; mu < 4; ++mu) out[mu] = smom[(i * 4 + mu) * BLOCK + l];
 }
 
+// Split form for software pipelining: the LDS loads of the legs in MASK into
+// registers (one laundered lane index), issued ahead of a scheduling barrier,
+// and their signed sum, which the scheduler places after it.  The sum takes
+// the legs in the same order and with the same operations as
+// flow_momentum_lds, so both give the same bits.
+template <unsigned MASK, int NEXT, int BLOCK>
+__device__ __forceinline__ void load_legs_lds(double (&r)[NEXT][4], const double* smom, int lane) {
+  const int l = fresh_lane(lane);
+#pragma unroll
+  for (int i = 0; i < NEXT; ++i)
+    if (MASK & (1u << i))
+#pragma unroll
+      for (int mu = 0; mu < 4; ++mu) r[i][mu] = smom[(i * 4 + mu) * BLOCK + l];
+}
+// The barrier between the two, in FP64 only: there one wave per SIMD leaves
+// the load latency exposed unless the loads are issued early, while the FP32
+// kernels run two waves per SIMD and would lose the second one to the longer
+// live ranges.
+template <typename T> __device__ __forceinline__ void pf_barrier() {
+  if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
+}
+template <unsigned MASK, unsigned INMASK, int NEXT>
+__device__ __forceinline__ void sum_legs(double out[4], const double (&r)[NEXT][4]) {
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NEXT; ++i)
+      if (MASK & (1u << i)) acc = (INMASK & (1u << i)) ? acc + r[i][mu] : acc - r[i][mu];
+    out[mu] = acc;
+  }
+}
+
 // External wavefunctions staged per lane in LDS: the eight real components
 // of leg i at s[(i*8 + k)*NL + lane].  Each use loads them again through a
 // laundered lane index, so none stays in registers between uses.
