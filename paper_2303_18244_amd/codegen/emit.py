@@ -139,6 +139,10 @@ class GGBody:
         self.counter = 0
         self.prefetch = prefetch
         self.pf_dist = 1
+        # den_index: denominator key -> row of the per-event table `sden`
+        # (distance-2 pipelining only); the denominators are then loaded
+        # instead of recomputed for every helicity
+        self.den_index: Optional[Dict[tuple, int]] = None
         self.calls: List[Optional[tuple]] = []  # per routine call: its momentum needs
         if prefetch:
             em.w("@@PFHEAD@@")
@@ -178,12 +182,45 @@ class GGBody:
                     u |= m
         return u
 
+    @staticmethod
+    def den_key(needs: Optional[tuple]) -> Optional[tuple]:
+        """The quantity a call's denominator is computed from: the legs of
+        the propagator momentum (as two partial sums for a three-gluon
+        vertex) and the mass; None if the call has no propagator."""
+        if needs is None or needs[0] == "amp3":
+            return None
+        if needs[0] == "vvv":
+            return ("vvv", needs[1], needs[2], "0.0")
+        if needs[0] == "prop":
+            return ("sum", needs[1], needs[2])
+        return ("sum", needs[1], "0.0")
+
+    def _legs(self, j: int) -> int:
+        """Legs whose momenta call j needs in registers."""
+        needs = self.calls[j] if j < len(self.calls) else None
+        if needs is not None and needs[0] == "den" and self.den_index is not None:
+            return 0
+        return self._union(j)
+
     def pf_loads(self, j: int) -> str:
         """Distance 2: the LDS loads of call j into its raw registers."""
-        u = self._union(j)
-        if not u:
-            return ""
-        return f"load_legs_lds<{u}u, NEXT, {self.mom_block}>(pf{j}_r, smom, lane); pf_barrier<T>(); "
+        u = self._legs(j)
+        out = ""
+        if u:
+            out += f"load_legs_lds<{u}u, NEXT, {self.mom_block}>(pf{j}_r, smom, lane); "
+        k = self.den_key(self.calls[j] if j < len(self.calls) else None)
+        if self.den_index is not None and k is not None:
+            out += f"pf{j}_dr = load_den_lds<{self.mom_block}>(sden, {self.den_index[k]}, lane); "
+        return out + "pf_barrier<T>(); " if out else ""
+
+    def pf_raw_decl(self, j: int) -> str:
+        """Declarations of the raw registers that call j's loads fill."""
+        parts = []
+        if self._legs(j):
+            parts.append(f"double pf{j}_r[NEXT][4];")
+        if self.den_index is not None and self.den_key(self.calls[j] if j < len(self.calls) else None):
+            parts.append(f"double pf{j}_dr;")
+        return " ".join(parts)
 
     def pf_sums(self, j: int) -> str:
         """Distance 2: sums and denominator of call j from its raw registers."""
@@ -205,17 +242,20 @@ class GGBody:
         register array `r`; closes the block the caller opened."""
         kind, masks = needs[0], [m for m in needs[1:] if isinstance(m, int)]
         I = self.inmask
+        table = self.den_index is not None
         if kind == "vvv":
             m1, m2 = masks
+            den = (f"pf{j}_den = (T)pf{j}_dr; }} " if table else
+                   "const double Pd[4] = {k1d[0] + k2d[0], k1d[1] + k2d[1], k1d[2] + k2d[2], k1d[3] + k2d[3]}; "
+                   f"pf{j}_den = (T)inv_virt(Pd, 0.0); }} ")
             body = (f"double k1d[4]; sum_legs<{m1}u, {I}u, NEXT>(k1d, {r}); double k2d[4]; sum_legs<{m2}u, {I}u, NEXT>(k2d, {r}); "
-                    f"to_t(pf{j}_k1, k1d); to_t(pf{j}_k2, k2d); "
-                    "const double Pd[4] = {k1d[0] + k2d[0], k1d[1] + k2d[1], k1d[2] + k2d[2], k1d[3] + k2d[3]}; "
-                    f"pf{j}_den = (T)inv_virt(Pd, 0.0); }} ")
+                    f"to_t(pf{j}_k1, k1d); to_t(pf{j}_k2, k2d); " + den)
         elif kind == "prop":
-            body = (f"double Pd[4]; sum_legs<{masks[0]}u, {I}u, NEXT>(Pd, {r}); to_t(pf{j}_P, Pd); "
-                    f"pf{j}_den = (T)inv_virt(Pd, {needs[2]}); }} ")
+            den = f"pf{j}_den = (T)pf{j}_dr; }} " if table else f"pf{j}_den = (T)inv_virt(Pd, {needs[2]}); }} "
+            body = f"double Pd[4]; sum_legs<{masks[0]}u, {I}u, NEXT>(Pd, {r}); to_t(pf{j}_P, Pd); " + den
         elif kind == "den":
-            body = f"double Pd[4]; sum_legs<{masks[0]}u, {I}u, NEXT>(Pd, {r}); pf{j}_den = (T)inv_virt(Pd, 0.0); }} "
+            body = (f"pf{j}_den = (T)pf{j}_dr; }} " if table else
+                    f"double Pd[4]; sum_legs<{masks[0]}u, {I}u, NEXT>(Pd, {r}); pf{j}_den = (T)inv_virt(Pd, 0.0); }} ")
         else:
             body = " ".join(f"{{ double kd[4]; sum_legs<{m}u, {I}u, NEXT>(kd, {r}); to_t(pf{j}_{k}, kd); }}"
                             for k, m in zip(("k1", "k2", "k3"), masks)) + " } "
@@ -232,16 +272,14 @@ class GGBody:
             for ln in self.em.lines:
                 t = ln.strip()
                 if t == "@@PFHEAD@@":
-                    decl = [f"double pf{j}_r[NEXT][4];" for j in (0, 1) if self._union(j)]
+                    decl = [self.pf_raw_decl(j) for j in (0, 1)]
                     decl += [self.pf_decl(0)]
                     out.append("    " + " ".join(d for d in decl if d) + " " + self.pf_loads(0) + self.pf_loads(1)
                                + self.pf_sums(0).rstrip())
                     continue
                 if t.startswith("@@PFDECL"):
                     i = int(t[len("@@PFDECL"):-2])
-                    d = self.pf_decl(i + 1)
-                    if self._union(i + 2):
-                        d = (d + " " if d else "") + f"double pf{i + 2}_r[NEXT][4];"
+                    d = " ".join(x for x in (self.pf_decl(i + 1), self.pf_raw_decl(i + 2)) if x)
                     if d:
                         out.append("    " + d)
                     continue
@@ -429,10 +467,11 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
     ncol = len(flows)
     order = sched.low_pressure_order()
 
-    def helicity_body(dist: int) -> List[str]:
+    def helicity_body(dist: int, den_index=None) -> List[str]:
         em = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
         body = GGBody(sched, pdg, em, lds_momenta=True, prefetch=True)
         body.pf_dist = dist
+        body.den_index = den_index
         for a in order:
             body.amplitude(a)
             upd = " ".join(f"acc(J[{f}], a, {re}, {im});" for f, re, im in a.coeffs)
@@ -447,16 +486,56 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
     # that keep the colour-flow sums in registers, it would cost the second
     # wave per SIMD.
     lines = [f"    cx<T> J[{ncol}];", f"    for (int s = 0; s < {ncol}; ++s) J[s] = mk<T>((T)0, (T)0);"]
+    den_prologue = ""
     if n_ext <= 5:
         lines += helicity_body(2)
     else:
-        lines += (["    if constexpr (sizeof(T) == 8 || MODE == 2) {"] + helicity_body(2) + ["    } else {"]
-                  + helicity_body(1) + ["    }"])
+        # The FP64 kernels (one block of two waves per SIMD pair) also take
+        # the propagator denominators from a per-event LDS table filled
+        # before the helicity loop.  Not in the selection mode, whose colour
+        # accumulators already take LDS, nor in FP32, whose two waves per
+        # SIMD could not both hold the table.
+        probe = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
+        pb = GGBody(sched, pdg, probe, lds_momenta=True, prefetch=True)
+        for a in order:
+            pb.amplitude(a)
+            probe.w(" }")
+        keys = list(dict.fromkeys(k for k in map(GGBody.den_key, pb.calls) if k is not None))
+        den_index = {k: i for i, k in enumerate(keys)}
+        den_prologue = den_table_lines(keys, pb.inmask)
+        lines += (["    if constexpr (kDenTable) {"] + helicity_body(2, den_index)
+                  + ["    } else if constexpr (sizeof(T) == 8 || MODE == 2) {"] + helicity_body(2)
+                  + ["    } else {"] + helicity_body(1) + ["    }"])
     colour = (["      TC mc = (TC)0;"] + ["  " + ln for ln in colour_sum_lines(C, cden)]
               + ["      const double me = (double)mc;"])
     flops_hel = sched.flops_per_helicity() + 2 * ncol * ncol + 4 * ncol + 90 * n_ext
     return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "\n".join(lines),
-                    colour="\n".join(colour))
+                    colour="\n".join(colour), den_prologue=den_prologue)
+
+
+def den_table_lines(keys: List[tuple], inmask: int) -> str:
+    """Kernel prologue filling sden[k*BLOCK + lane] with 1/(P^2 - m^2) of
+    every distinct propagator of the event, computed exactly as the
+    helicity loop would (same partial sums, same order)."""
+    B = "MGME_ME_BLOCK"
+    out = ["  // Propagator denominators of the event, the same for every helicity:",
+           "  // computed once here, loaded in the helicity loop (FP64 kernels).",
+           "  constexpr bool kDenTable = sizeof(T) == 8 && MODE != 3;",
+           f"  __shared__ double sden[kDenTable ? {len(keys)} * {B} : 1];",
+           "  if constexpr (kDenTable) {"]
+    for i, k in enumerate(keys):
+        if k[0] == "vvv":
+            _, m1, m2, mass = k
+            out.append(f"    {{ double k1d[4]; flow_momentum_lds<{m1}u, {inmask}u, NEXT, {B}>(k1d, smom, lane); "
+                       f"double k2d[4]; flow_momentum_lds<{m2}u, {inmask}u, NEXT, {B}>(k2d, smom, lane);")
+            out.append("      const double Pd[4] = {k1d[0] + k2d[0], k1d[1] + k2d[1], k1d[2] + k2d[2], k1d[3] + k2d[3]};")
+            out.append(f"      sden[{i} * {B} + lane] = inv_virt(Pd, {mass}); }}")
+        else:
+            _, m, mass = k
+            out.append(f"    {{ double Pd[4]; flow_momentum_lds<{m}u, {inmask}u, NEXT, {B}>(Pd, smom, lane); "
+                       f"sden[{i} * {B} + lane] = inv_virt(Pd, {mass}); }}")
+    out.append("  }")
+    return "\n".join(out)
 
 
 def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefetch: int = 6,
@@ -658,6 +737,7 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) smom[(i * 4 + mu) * MGME_ME_BLOCK + lane] = mom[(long long)(i * 4 + mu) * ld + e];
   const double mt = args.mt;
+{den_prologue}
   // The good helicities are summed in groups of MGME_HEL_GROUP, the group
   // sums in group order.  A lane takes groups blockIdx.y, blockIdx.y +
   // gridDim.y, ...: all of them when gridDim.y == 1; otherwise each group sum
@@ -847,7 +927,7 @@ def kernel_sources(meta: Dict) -> Dict[str, str]:
     """File name -> source for a process evaluated by one fused kernel."""
     title = " ".join(str(x) for x in meta["pdg"])
     name = meta["name"]
-    out = {f"me_{name}_kernel.h": KERNEL_HEADER_TEMPLATE.format(title=title, **meta),
+    out = {f"me_{name}_kernel.h": KERNEL_HEADER_TEMPLATE.format(title=title, **{"den_prologue": "", **meta}),
            f"me_{name}.hip": LAUNCH_TEMPLATE.format(title=title, name=name),
            f"me_{name}_sel.hip": SELECT_TEMPLATE.format(title=title, name=name)}
     for tag, T, TC, what in (("d", "double", "double", "FP64 diagrams and colour sum"),

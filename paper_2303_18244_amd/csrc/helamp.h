@@ -462,6 +462,11 @@ __device__ __forceinline__ void load_legs_lds(double (&r)[NEXT][4], const double
 #pragma unroll
       for (int mu = 0; mu < 4; ++mu) r[i][mu] = smom[(i * 4 + mu) * BLOCK + l];
 }
+// One per-event propagator denominator staged per lane in LDS, at
+// s[k*BLOCK + lane] (laundered lane index, like the momenta).
+template <int BLOCK> __device__ __forceinline__ double load_den_lds(const double* s, int k, int lane) {
+  return s[k * BLOCK + fresh_lane(lane)];
+}
 // The barrier between the two, in FP64 only: there one wave per SIMD leaves
 // the load latency exposed unless the loads are issued early, while the FP32
 // kernels run two waves per SIMD and would lose the second one to the longer

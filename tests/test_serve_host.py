@@ -24,12 +24,15 @@ def test_slots_budget_and_latency():
     st = S.stats()
     S.close()
     assert st["completed"] == len(sizes) and st["failed"] == 0 and st["events"] == sum(sizes)
-    assert 1 <= st["max_concurrent"] <= 3
+    # the requests overlap (the scheduler's own count), within the slot limit
+    assert 2 <= st["max_concurrent"] <= 3
     assert st["peak_workspace_bytes"] <= 5_000_000
-    # every request lasts at least its scripted duration, and they overlap:
+    # every request lasts at least its scripted duration; overlapped, the
+    # whole batch takes less than the same requests one after another (a
+    # loose wall-clock bound, so that host scheduling jitter cannot fail it)
     for n, lat in zip(sizes, lats):
         assert lat >= n * 2000e-6 * 0.99
-    assert wall < sum(sizes) * 2000e-9 * 0.9
+    assert wall < sum(sizes) * 2000e-9
     assert st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
 
 
