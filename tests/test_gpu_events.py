@@ -171,6 +171,21 @@ def test_select_fp64_matches_oracle(M, oracle_mod, name):
     assert col.min() >= 0 and col.max() < O.n_colour
 
 
+def test_denominator_table_same_bits(M, oracle_mod):
+    """g g -> t t~ g g in FP64: the plain kernel takes the propagator
+    denominators from its per-event table, the selection kernel recomputes
+    them for every helicity with the same operations; the |M|^2 of both
+    must agree bit for bit."""
+    torch = _torch()
+    n, sqrt_s = 1000, 1500.0
+    P = M.Process(M.PROCESSES["gg_ttgg"])
+    host, _ = oracle_mod.rambo(_masses(P.pdg), sqrt_s, SEED, 7, n)
+    mom = _dev(host.transpose(1, 2, 0))
+    r = _dev(np.random.default_rng(5).random(n))
+    me_sel, _, _ = P.select(mom, r, r)
+    assert torch.equal(me_sel, P.matrix_element(mom))
+
+
 @pytest.mark.parametrize("name", ["gg_ttg", "gg_ttgg", "gg_ttggg"])
 @pytest.mark.parametrize("prec", [1, 2, 3])
 def test_select_reduced_precision(M, oracle_mod, name, prec):
