@@ -487,14 +487,15 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
     # wave per SIMD.
     lines = [f"    cx<T> J[{ncol}];", f"    for (int s = 0; s < {ncol}; ++s) J[s] = mk<T>((T)0, (T)0);"]
     den_prologue = ""
+    j2_regs = "false"
     if n_ext <= 5:
         lines += helicity_body(2)
     else:
         # The FP64 kernels (one block of two waves per SIMD pair) also take
         # the propagator denominators from a per-event LDS table filled
-        # before the helicity loop.  Not in the selection mode, whose colour
-        # accumulators already take LDS, nor in FP32, whose two waves per
-        # SIMD could not both hold the table.
+        # before the helicity loop; their selection mode keeps its colour
+        # accumulators in registers to leave the LDS to the table.  Not in
+        # FP32, whose two waves per SIMD could not both hold the table.
         probe = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
         pb = GGBody(sched, pdg, probe, lds_momenta=True, prefetch=True)
         for a in order:
@@ -503,6 +504,7 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
         keys = list(dict.fromkeys(k for k in map(GGBody.den_key, pb.calls) if k is not None))
         den_index = {k: i for i, k in enumerate(keys)}
         den_prologue = den_table_lines(keys, pb.inmask)
+        j2_regs = "sizeof(T) == 8"
         lines += (["    if constexpr (kDenTable) {"] + helicity_body(2, den_index)
                   + ["    } else if constexpr (sizeof(T) == 8 || MODE == 2) {"] + helicity_body(2)
                   + ["    } else {"] + helicity_body(1) + ["    }"])
@@ -510,7 +512,7 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
               + ["      const double me = (double)mc;"])
     flops_hel = sched.flops_per_helicity() + 2 * ncol * ncol + 4 * ncol + 90 * n_ext
     return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "\n".join(lines),
-                    colour="\n".join(colour), den_prologue=den_prologue)
+                    colour="\n".join(colour), den_prologue=den_prologue, j2_regs=j2_regs)
 
 
 def den_table_lines(keys: List[tuple], inmask: int) -> str:
@@ -520,7 +522,7 @@ def den_table_lines(keys: List[tuple], inmask: int) -> str:
     B = "MGME_ME_BLOCK"
     out = ["  // Propagator denominators of the event, the same for every helicity:",
            "  // computed once here, loaded in the helicity loop (FP64 kernels).",
-           "  constexpr bool kDenTable = sizeof(T) == 8 && MODE != 3;",
+           "  constexpr bool kDenTable = sizeof(T) == 8;",
            f"  __shared__ double sden[kDenTable ? {len(keys)} * {B} : 1];",
            "  if constexpr (kDenTable) {"]
     for i, k in enumerate(keys):
@@ -722,11 +724,17 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nevt) return;
   const int lane = threadIdx.x;
-  // per-lane jamp^2 accumulators (MODE 3), [flow][lane of the block]
-  __shared__ double j2[MODE == 3 ? NCOL * MGME_ME_BLOCK : 1];
+  // per-lane jamp^2 accumulators (MODE 3): in registers where LDS is needed
+  // for the denominator table, else in LDS, [flow][lane of the block]
+  constexpr bool kJ2Regs = {j2_regs};
+  __shared__ double j2[MODE == 3 && !kJ2Regs ? NCOL * MGME_ME_BLOCK : 1];
+  double j2r[MODE == 3 && kJ2Regs ? NCOL : 1];
   if constexpr (MODE == 3) {{
 #pragma unroll
-    for (int s = 0; s < NCOL; ++s) j2[s * MGME_ME_BLOCK + lane] = 0.0;
+    for (int s = 0; s < NCOL; ++s) {{
+      if constexpr (kJ2Regs) j2r[s] = 0.0;
+      else j2[s * MGME_ME_BLOCK + lane] = 0.0;
+    }}
   }}
   // The lane's momenta stay in LDS: every momentum-dependent quantity is
   // derived again inside the helicity loop where it is needed, instead of
@@ -764,8 +772,11 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
         if constexpr (MODE == 3) {{
           aux[(long long)ih * lda + e] = me;
 #pragma unroll
-          for (int s = 0; s < NCOL; ++s)
-            j2[s * MGME_ME_BLOCK + threadIdx.x] += (double)J[s].re * (double)J[s].re + (double)J[s].im * (double)J[s].im;
+          for (int s = 0; s < NCOL; ++s) {{
+            const double a2 = (double)J[s].re * (double)J[s].re + (double)J[s].im * (double)J[s].im;
+            if constexpr (kJ2Regs) j2r[s] += a2;
+            else j2[s * MGME_ME_BLOCK + threadIdx.x] += a2;
+          }}
         }}
       }}
     }}
@@ -780,7 +791,8 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
   }}
   if constexpr (MODE == 3) {{
 #pragma unroll
-    for (int s = 0; s < NCOL; ++s) aux[(long long)(args.nhel + s) * lda + e] = j2[s * MGME_ME_BLOCK + threadIdx.x];
+    for (int s = 0; s < NCOL; ++s)
+      aux[(long long)(args.nhel + s) * lda + e] = kJ2Regs ? j2r[s] : j2[s * MGME_ME_BLOCK + threadIdx.x];
   }}
 }}
 
@@ -927,7 +939,8 @@ def kernel_sources(meta: Dict) -> Dict[str, str]:
     """File name -> source for a process evaluated by one fused kernel."""
     title = " ".join(str(x) for x in meta["pdg"])
     name = meta["name"]
-    out = {f"me_{name}_kernel.h": KERNEL_HEADER_TEMPLATE.format(title=title, **{"den_prologue": "", **meta}),
+    out = {f"me_{name}_kernel.h": KERNEL_HEADER_TEMPLATE.format(
+        title=title, **{"den_prologue": "", "j2_regs": "false", **meta}),
            f"me_{name}.hip": LAUNCH_TEMPLATE.format(title=title, name=name),
            f"me_{name}_sel.hip": SELECT_TEMPLATE.format(title=title, name=name)}
     for tag, T, TC, what in (("d", "double", "double", "FP64 diagrams and colour sum"),
