@@ -70,3 +70,52 @@ def test_schedule_covers_every_term_once(name):
     order = S.low_pressure_order()
     assert sorted(id(a) for a in order) == sorted(id(a) for a in S.amps)
     assert S.flops_per_helicity() > 0
+
+
+@pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
+def test_software_pipelined_body_is_well_formed(name):
+    """The fused kernels' helicity bodies with momenta (and, for g g -> t t~
+    g g in FP64, denominators) loaded one or two routine calls ahead: no
+    placeholder is left, every prefetched value is declared once, assigned
+    in an earlier statement than the call that uses it, and used once; the
+    per-event denominator table has one row per distinct denominator."""
+    import re
+
+    from paper_2303_18244_amd.build import PROCESSES
+    from paper_2303_18244_amd.codegen.emit import emit_gg_process
+
+    meta = emit_gg_process(name, PROCESSES[name])
+    body = meta["body"]
+    assert "@@" not in body
+    lines = body.split("\n")
+    forms = [i for i, ln in enumerate(lines) if ln.strip().startswith(("if constexpr", "} else"))]
+    bounds = [0] + forms + [len(lines)]
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        seg = lines[a:b]
+        declared, assigned, used = {}, {}, {}
+        for i, ln in enumerate(seg):
+            for v in re.findall(r"\b(?:T|double) (pf\d+_(?:k1|k2|k3|P|den|r|dr))\b", ln):
+                assert v not in declared, (name, v)
+                declared[v] = i
+            for v in re.findall(r"\b(pf\d+_(?:den|dr))\s*=", ln):
+                assigned.setdefault(v, i)
+            for v in re.findall(r"to_t\((pf\d+_(?:k1|k2|k3|P)),", ln):
+                assigned.setdefault(v, i)
+            for v in re.findall(r"load_legs_lds<\d+u, NEXT, \w+>\((pf\d+_r),", ln):
+                assigned.setdefault(v, i)
+            for v in re.findall(r"(?:vvv_vec|vvvv_vec|ket_prop|bra_prop|ffv_vec|vvv_amp)<[^>]*>\(([^;]*)\);", ln):
+                for u in re.findall(r"\b(pf\d+_(?:k1|k2|k3|P|den))\b", v):
+                    used.setdefault(u, []).append(i)
+        for v, uses in used.items():
+            assert len(uses) == 1, (name, v)
+            assert v in declared and v in assigned, (name, v)
+            assert declared[v] <= assigned[v] <= uses[0], (name, v, declared[v], assigned[v], uses[0])
+        # every prefetched value a call needs is used by that call
+        for v in declared:
+            if v.endswith(("_r", "_dr")):
+                continue
+            assert v in used, (name, v)
+    if name == "gg_ttgg":
+        rows = re.findall(r"sden\[(\d+) \* MGME_ME_BLOCK \+ lane\] = inv_virt", meta["den_prologue"])
+        assert [int(r) for r in rows] == list(range(44))
+        assert body.count("if constexpr (kDenTable)") == 1
