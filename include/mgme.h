@@ -47,7 +47,8 @@ typedef enum {
   MGME_FP32 = 1, /* diagrams in single precision; momenta, propagator denominators,
                     colour quadratic form and helicity sum in double */
   MGME_MIXED = 2, /* single-precision diagrams; colour sum on the matrix cores with J split into two
-                     power-of-two-scaled half-precision parts (FP32 accumulation); helicity sum in double */
+                     power-of-two-scaled half-precision parts (FP32 accumulation of C J, the dot product
+                     J^dagger (C J) in double); helicity sum in double */
   MGME_FP64_FP32COLOUR = 3 /* the "mixed" mode of the paper (section 3, Table 3): diagrams and J in
                               double, colour algebra Re(J^dagger C J) in single precision, helicity sum
                               in double */
@@ -121,10 +122,11 @@ int mgme_rambo(const mgme_process* proc, double sqrt_s, unsigned long long seed,
 
 /* |M|^2 per event, summed over the good helicities and all colours and
  * normalised by norm_factor, into d_me[nevt] (FP64 in every precision).
- * Processes with many colour flows (g g -> t t~ g g g), and MGME_MIXED for
- * every process, stage colour-flow amplitudes in a workspace taken from the
- * stream-ordered allocator (hipMallocAsync) and returned at the end of the
- * call (at most a few GB, on `hip_stream`).  A batch too small to give every
+ * Processes with many colour flows (g g -> t t~ g g g) stage colour-flow
+ * amplitudes in a workspace taken from the stream-ordered allocator
+ * (hipMallocAsync) and returned at the end of the call (at most a few GB, on
+ * `hip_stream`); the other processes form every precision's colour sum,
+ * MGME_MIXED's on the matrix cores, inside the diagram kernel.  A batch too small to give every
  * SIMD several waves spreads its helicities, in groups of 8, over more lanes
  * and takes 8 bytes per group and event for the partial sums; the group sums
  * are added in the same order whatever the batch size, so an event's |M|^2
@@ -205,40 +207,71 @@ const char* mgme_last_error(void);
  * sizes on one GPU (the paper's observation that several clients sharing a
  * GPU raise its combined throughput, section 2, Fig. 1).  Requests are queued
  * on submission; a scheduler thread admits them in arrival order onto free
- * slots (one stream each) whenever the summed device workspace of the running
- * requests stays within the budget (see mgme_workspace_bytes), passing over a
- * request that does not fit in favour of a later one that does; a request
- * larger than the whole budget runs alone.  Admitted requests run
- * concurrently.  Each request runs exactly the kernels of a standalone
- * mgme_matrix_element call, so its result does not depend on the others. */
+ * slots (one stream each) whenever the summed HBM footprint of the running
+ * requests stays within the budget.  The footprint of n events is
+ * n * (32 n_ext + 8) bytes of momenta and results plus the staging workspace
+ * of mgme_workspace_bytes (without graphs; with graphs the staging belongs to
+ * the slots).  A request that does not fit may be passed over by a later one
+ * that does, at most max_pass_over times; after that nothing behind it is
+ * admitted until it fits, so a large request cannot starve.  A request whose
+ * footprint exceeds the whole budget is split into parts of a multiple of 64
+ * events that fit (a part of 64 events that still does not fit runs alone).
+ * Admitted requests run concurrently.  Each request (or part) runs exactly the
+ * kernels of a standalone mgme_matrix_element call, so its result does not
+ * depend on the others or on the split: an event's |M|^2 does not depend on
+ * the batch it is in. */
 typedef struct mgme_server mgme_server;
 
 typedef struct {
   int n_slots;                  /* requests running at once (1..64) */
-  long long hbm_budget_bytes;   /* bound on the summed workspace of running requests */
+  long long hbm_budget_bytes;   /* bound on the summed footprint of running requests; 0: 0.8 x the
+                                   free device memory at creation (hipMemGetInfo, after the slot
+                                   workspaces are allocated); the test double: 0 is no bound */
+  int use_graphs;               /* 1: each request's launches are captured into a HIP graph on its
+                                   slot's stream and replayed; an instantiated graph is kept per
+                                   (slot, process, precision, power-of-two batch size) and updated
+                                   for the next request of that kind */
+  long long slot_workspace_bytes; /* with graphs: device staging buffer owned by each slot and
+                                     allocated at creation, outside any graph (0: 1 GiB); the
+                                     staged processes run in sub-batches that fit it */
+  int max_pass_over;            /* times a queued request may be passed over (0: 4) */
   int fake_executor;            /* 1: test double, no device work: a request completes
                                    fake_ns_per_event * nevt ns after admission, footprint
                                    fake_bytes_per_event * nevt; process and device pointers unused */
   double fake_ns_per_event;
   long long fake_bytes_per_event;
+  long long fake_fail_nevt;     /* test double: a request (or part) of exactly this many events
+                                   fails with MGME_EDEVICE (0: none fails) */
 } mgme_server_config;
 
 typedef struct {
   long long submitted, completed, failed, events;
   double p50_ms, p99_ms, mean_ms, max_ms; /* submission-to-completion latency of completed requests */
   double wall_s;                          /* first submission to last completion */
-  int max_concurrent;                     /* most requests running at once */
-  long long peak_workspace_bytes;         /* largest summed workspace of running requests */
+  int max_concurrent;                     /* most requests (or parts) running at once */
+  long long peak_footprint_bytes;         /* largest summed footprint of running requests */
+  long long budget_bytes;                 /* the budget in force (0: none) */
+  long long split_requests;               /* requests split into parts */
+  long long graph_launches;               /* graph replays (use_graphs) */
+  long long graph_instantiations;         /* graphs instantiated (the rest were updated in place) */
 } mgme_server_stats;
 
+/* Starts a server on `device`.  Errors: EINVAL (bad configuration), ENOMEM
+ * (slot workspace), EDEVICE. */
 int mgme_server_create(const mgme_server_config* cfg, int device, mgme_server** out);
 /* Queues |M|^2 of one batch (arguments as mgme_matrix_element; every pointer
  * must stay valid, and the process alive, until the request completes).
- * *id identifies the request for mgme_server_wait. */
+ * hip_stream is the caller's stream that produced d_mom and last wrote d_me:
+ * the request's kernels start only after the work enqueued on it before this
+ * call (an event is recorded there; NULL is the null stream).  Results are
+ * ready when mgme_server_wait returns.  *id identifies the request for
+ * mgme_server_wait.  Errors: EINVAL (bad batch, or with graphs a slot
+ * workspace too small for the process), EDEVICE. */
 int mgme_server_submit(mgme_server* s, const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
-                       int precision, double* d_me, unsigned long long* id);
-/* Blocks until request `id` completed; returns its status and releases it
- * (each request is waited for at most once). */
+                       int precision, double* d_me, void* hip_stream, unsigned long long* id);
+/* Blocks until request `id` completed; returns its status (MGME_OK, or the
+ * error of its launch or of any of its parts) and releases it (each request is
+ * waited for at most once). */
 int mgme_server_wait(mgme_server* s, unsigned long long id, double* latency_ms);
 /* Blocks until no request is queued or running. */
 int mgme_server_drain(mgme_server* s);

@@ -70,6 +70,7 @@ def lib():
         L.oracle_me.argtypes = [ctypes.c_void_p, dp, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_int, dp]
         L.oracle_me_hel.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
+        L.oracle_condition.argtypes = [ctypes.c_void_p, dp, dp]
         L.oracle_gauge.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
         L.oracle_flows.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp]
         L.oracle_event_weights.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, dp, dp]
@@ -220,6 +221,13 @@ class Process:
         margin = np.zeros(2)
         lib().oracle_select(self._h, _dp(mom1), r_hel, r_col, out, _dp(margin))
         return int(out[0]), int(out[1]), margin
+
+    def condition(self, mom1: np.ndarray) -> float:
+        """Condition number of |M|^2 for one event (see oracle.h)."""
+        mom1 = np.ascontiguousarray(mom1, dtype=np.float64)
+        out = np.zeros(1)
+        lib().oracle_condition(self._h, _dp(mom1), _dp(out))
+        return float(out[0])
 
     def gauge(self, mom1: np.ndarray, leg: int):
         mom1 = np.ascontiguousarray(mom1, dtype=np.float64)

@@ -136,9 +136,15 @@ int oracle_me_hel(void* proc, const double* mom, int precision, double* me_hel) 
   return 0;
 }
 
+int oracle_condition(void* proc, const double* mom, double* kappa) {
+  auto* P = static_cast<oracle::Process*>(proc);
+  *kappa = (double)P->condition(mom);
+  return 0;
+}
+
 int oracle_gauge(void* proc, const double* mom, int leg, double out[2]) {
   auto* P = static_cast<oracle::Process*>(proc);
-  if (P->kind != oracle::Process::GG_TT_NG || P->pdg[leg] != 21) return -1;
+  if (P->kind != oracle::Process::GG_TT_NG || leg < 0 || leg >= P->n_ext || P->pdg[leg] != 21) return -1;
   const auto ev = P->make_event<double>(mom);
   std::vector<std::complex<double>> amp, J;
   double mx_rep = 0, mx = 0;

@@ -50,6 +50,12 @@ int oracle_me(void* proc, const double* mom, int64_t nevt, int colour_mode, int 
               int nthreads, double* me);
 /* Per-helicity colour-summed |M_h|^2 for one event (n_hel values). */
 int oracle_me_hel(void* proc, const double* mom, int precision, double* me_hel);
+/* Condition number of |M|^2 for one event: the helicity- and colour-summed
+ * square with every diagram amplitude, colour coefficient and colour-matrix
+ * entry replaced by its absolute value, over |M|^2 (long double inside).
+ * Relative changes of at most eps in every amplitude change |M|^2 by at most
+ * about 2 eps kappa relative; it scales the FP64 rounding of an event. */
+int oracle_condition(void* proc, const double* mom, double* kappa);
 /* Gauge test: replace the polarisation of gluon `leg` by its momentum.
  * out[0] = max over helicities and flows of |J_s| with the replacement,
  * out[1] = the same maximum without it. */

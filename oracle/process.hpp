@@ -664,6 +664,34 @@ class Process {
     }
   }
 
+  // Condition number of |M|^2 with respect to relative changes of the
+  // diagram amplitudes: the same helicity and colour sums with every term
+  // amplitude, colour coefficient and colour-matrix entry replaced by its
+  // absolute value, divided by |M|^2 itself.  Changing each amplitude by a
+  // relative amount of at most eps changes |M|^2 by at most about
+  // 2 eps kappa |M|^2; kappa >= 1, and it is large where diagrams cancel.
+  long double condition(const double* mom) const {
+    using L = long double;
+    const Event<L> ev = make_event<L>(mom);
+    std::vector<cplx<L>> amp, J;
+    std::vector<L> Ja(ncol);
+    L num = 0, den = 0;
+    for (int h = 0; h < n_hel; ++h) {
+      term_amplitudes(ev, h, -1, amp);
+      flows(amp, J);
+      den += colour_sum(J);
+      std::fill(Ja.begin(), Ja.end(), (L)0);
+      for (size_t t = 0; t < terms.size(); ++t)
+        for (auto& sc : coef[t]) Ja[sc.first] += std::abs(cplx<L>((L)sc.second.real(), (L)sc.second.imag())) *
+                                                 std::abs(amp[t]);
+      L a = 0;
+      for (int s = 0; s < ncol; ++s)
+        for (int t = 0; t < ncol; ++t) a += std::abs((L)cnum[(size_t)s * ncol + t]) * Ja[s] * Ja[t];
+      num += a / (L)cden;
+    }
+    return num / den;
+  }
+
   template <class R> R me(const double* mom) const {
     std::vector<R> hel(n_hel);
     me_hel<R>(mom, hel.data());

@@ -38,15 +38,19 @@ EXPORTS = ["mgme_process_create", "mgme_process_destroy", "mgme_process_info", "
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("n_slots", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_longlong), ("fake_executor", ctypes.c_int),
-                ("fake_ns_per_event", ctypes.c_double), ("fake_bytes_per_event", ctypes.c_longlong)]
+    _fields_ = [("n_slots", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_longlong), ("use_graphs", ctypes.c_int),
+                ("slot_workspace_bytes", ctypes.c_longlong), ("max_pass_over", ctypes.c_int),
+                ("fake_executor", ctypes.c_int), ("fake_ns_per_event", ctypes.c_double),
+                ("fake_bytes_per_event", ctypes.c_longlong), ("fake_fail_nevt", ctypes.c_longlong)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong), ("failed", ctypes.c_longlong),
                 ("events", ctypes.c_longlong), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
                 ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("wall_s", ctypes.c_double),
-                ("max_concurrent", ctypes.c_int), ("peak_workspace_bytes", ctypes.c_longlong)]
+                ("max_concurrent", ctypes.c_int), ("peak_footprint_bytes", ctypes.c_longlong),
+                ("budget_bytes", ctypes.c_longlong), ("split_requests", ctypes.c_longlong),
+                ("graph_launches", ctypes.c_longlong), ("graph_instantiations", ctypes.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -101,7 +105,8 @@ def lib() -> ctypes.CDLL:
         L.mgme_event_weights.argtypes = [ctypes.c_double, dp, dp, i64, dp, dp, vp]
         L.mgme_unweight.argtypes = [dp, dp, i64, dp, vp, vp, vp]
         L.mgme_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.c_int, ctypes.POINTER(vp)]
-        L.mgme_server_submit.argtypes = [vp, vp, dp, i64, i64, ctypes.c_int, dp, ctypes.POINTER(ctypes.c_ulonglong)]
+        L.mgme_server_submit.argtypes = [vp, vp, dp, i64, i64, ctypes.c_int, dp, vp,
+                                         ctypes.POINTER(ctypes.c_ulonglong)]
         L.mgme_server_wait.argtypes = [vp, ctypes.c_ulonglong, ctypes.POINTER(ctypes.c_double)]
         L.mgme_server_drain.argtypes = [vp]
         L.mgme_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
@@ -276,27 +281,31 @@ class Server:
     include/mgme.h).  Tensors passed to submit() are kept referenced until
     their request has been waited for."""
 
-    def __init__(self, n_slots: int = 4, hbm_budget_bytes: int = 32 << 30, device: int = 0,
-                 fake_ns_per_event: Optional[float] = None, fake_bytes_per_event: int = 0):
-        cfg = ServerConfig(n_slots, hbm_budget_bytes, 1 if fake_ns_per_event is not None else 0,
-                           float(fake_ns_per_event or 0.0), int(fake_bytes_per_event))
+    def __init__(self, n_slots: int = 4, hbm_budget_bytes: int = 0, device: int = 0, use_graphs: bool = False,
+                 slot_workspace_bytes: int = 0, max_pass_over: int = 0, fake_ns_per_event: Optional[float] = None,
+                 fake_bytes_per_event: int = 0, fake_fail_nevt: int = 0):
+        cfg = ServerConfig(n_slots, hbm_budget_bytes, 1 if use_graphs else 0, slot_workspace_bytes, max_pass_over,
+                           1 if fake_ns_per_event is not None else 0, float(fake_ns_per_event or 0.0),
+                           int(fake_bytes_per_event), int(fake_fail_nevt))
         self._h = ctypes.c_void_p()
         _scheck(lib().mgme_server_create(ctypes.byref(cfg), device, ctypes.byref(self._h)))
         self._keep = {}
 
     def submit(self, proc: Optional[Process], mom=None, nevt: Optional[int] = None, precision: int = FP64,
-               out=None) -> int:
-        """Queues one batch; returns the request id.  With the test double,
-        proc, mom and out may be None (only nevt is used)."""
+               out=None, stream=None) -> int:
+        """Queues one batch; returns the request id.  The request starts after
+        the work already enqueued on `stream` (default: torch's current
+        stream), which produced `mom` and `out`.  With the test double, proc,
+        mom and out may be None (only nevt is used)."""
         rid = ctypes.c_ulonglong()
         if mom is None:
-            _scheck(lib().mgme_server_submit(self._h, None, None, int(nevt), int(nevt), int(precision), None,
+            _scheck(lib().mgme_server_submit(self._h, None, None, int(nevt), int(nevt), int(precision), None, None,
                                              ctypes.byref(rid)))
             return rid.value
         ld = mom.shape[-1]
         nevt = ld if nevt is None else nevt
         _scheck(lib().mgme_server_submit(self._h, proc._h, mom.data_ptr(), int(nevt), int(ld), int(precision),
-                                         out.data_ptr(), ctypes.byref(rid)))
+                                         out.data_ptr(), _stream_handle(stream), ctypes.byref(rid)))
         self._keep[rid.value] = (proc, mom, out)
         return rid.value
 

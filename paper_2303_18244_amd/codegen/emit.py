@@ -571,9 +571,13 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
     n_rmw = 0
     for chunk in chunks:
         em = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
-        # External wavefunctions are used without fresh copies here: with them
-        # the double-precision chunk kernels spill far more and returned wrong
-        # results on gfx950 (cause not isolated); without them they pass parity.
+        # External wavefunctions are used without register barriers here.  The
+        # variant with barriers (empty asm statements forcing each external
+        # wavefunction into VGPRs at every use) spills less, but its FP64 build
+        # returned wrong values on gfx950, while the same generated code
+        # compiled for the CPU is exact with and without the barriers: the
+        # defect lies in the device compilation of that variant, and a CPU test
+        # keeps the generator from emitting it.
         body = GGBody(sched, pdg, em, fresh_externals=False, inplace=inplace, lds_momenta=lds, mom_block="64",
                       ext_lds=lds)
         uses: Dict[int, List[int]] = {}
@@ -714,16 +718,33 @@ constexpr int NCOL = {ncol};
 //         Jout[(ih*NCOL + s)*ldo + e] (single precision) for the matrix-core colour sum;
 // MODE 3: as MODE 0, and for the helicity and colour choice each helicity's
 //         |M_h|^2 (before normalisation) into aux[ih*lda + e] and
-//         sum_h |J_s|^2 into aux[(nhel + s)*lda + e] (accumulated in LDS).
+//         sum_h |J_s|^2 into aux[(nhel + s)*lda + e] (accumulated in LDS);
+// MODE 4: as MODE 0, with the colour sum of every helicity on the matrix
+//         cores of the wave (single-precision J split into two half-precision
+//         parts, at most 32 flows).
+// MODE 4 is compiled for two waves per SIMD (the FP32 diagrams fit in 256
+// registers; the matrix-core accumulators would otherwise push the kernel to
+// AGPRs and one wave).
 template <typename T, int MODE, typename TC = double>
-__global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restrict__ mom, long long nevt,
-                                                          long long ld, const MeArgs args,
-                                                          double* __restrict__ out, long long ldo,
-                                                          float2* __restrict__ Jout, double* __restrict__ aux,
-                                                          long long lda) {{
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nevt) return;
+__global__ void __launch_bounds__(MGME_ME_BLOCK) __attribute__((amdgpu_waves_per_eu(MODE == 4 ? 2 : 1)))
+me_kernel(const double* __restrict__ mom, long long nevt, long long ld, const MeArgs args, double* __restrict__ out,
+          long long ldo, float2* __restrict__ Jout, double* __restrict__ aux, long long lda) {{
+  const long long e_raw = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // MODE 4 keeps every lane of a wave to the end (the colour sum runs across
+  // the wave's lanes): lanes past the batch evaluate its last event and store
+  // nothing
+  if constexpr (MODE != 4) {{
+    if (e_raw >= nevt) return;
+  }}
+  const bool e_live = e_raw < nevt;
+  const long long e = e_live ? e_raw : nevt - 1;
   const int lane = threadIdx.x;
+  mfma_half8 cfa[MODE == 4 ? 2 : 1];
+  if constexpr (MODE == 4) {{
+    const mfma_half8* cf = (const mfma_half8*)args.cfrag;
+    cfa[0] = cf[lane & 63];
+    cfa[1] = cf[64 + (lane & 63)];
+  }}
   // per-lane jamp^2 accumulators (MODE 3): in registers where LDS is needed
   // for the denominator table, else in LDS, [flow][lane of the block]
   constexpr bool kJ2Regs = {j2_regs};
@@ -763,6 +784,8 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
 #pragma unroll
       for (int s = 0; s < NCOL; ++s)
         Jout[((long long)ih * NCOL + s) * ldo + e] = make_float2((float)J[s].re, (float)J[s].im);
+    }} else if constexpr (MODE == 4) {{
+      part += colour_mfma_lane<NCOL>(J, cfa);
     }} else {{
 {colour}
       if constexpr (MODE == 1) {{
@@ -781,13 +804,13 @@ __global__ void __launch_bounds__(MGME_ME_BLOCK) me_kernel(const double* __restr
       }}
     }}
   }}
-  if constexpr (MODE == 0 || MODE == 3) {{
+  if constexpr (MODE == 0 || MODE == 3 || MODE == 4) {{
     if (gridDim.y == 1) total += part;
-    else aux[(long long)g * lda + e] = part;
+    else if (e_live) aux[(long long)g * lda + e] = part;
   }}
   }}
-  if constexpr (MODE == 0 || MODE == 3) {{
-    if (gridDim.y == 1) out[e] = total * args.factor;
+  if constexpr (MODE == 0 || MODE == 3 || MODE == 4) {{
+    if (gridDim.y == 1 && e_live) out[e] = total * args.factor;
   }}
   if constexpr (MODE == 3) {{
 #pragma unroll
@@ -807,29 +830,40 @@ LAUNCH_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: 
 
 extern "C" hipError_t mgme_select_{name}(int prec, const double* mom, long long nevt, long long ld,
                                           const mgme::MeArgs* args, double* out, const mgme::SelectArgs* sel,
-                                          hipStream_t stream);
+                                          const mgme::Workspace* wsp, hipStream_t stream);
 extern "C" hipError_t mgme_run_{name}_d(int per_hel, dim3 grid, const double* mom, long long nevt, long long ld,
-                                         const mgme::MeArgs* args, double* out, long long ldo, hipStream_t stream);
+                                         const mgme::MeArgs* args, double* out, long long ldo,
+                                         const mgme::Workspace* wsp, hipStream_t stream);
 extern "C" hipError_t mgme_run_{name}_f(int per_hel, dim3 grid, const double* mom, long long nevt, long long ld,
-                                         const mgme::MeArgs* args, double* out, long long ldo, hipStream_t stream);
+                                         const mgme::MeArgs* args, double* out, long long ldo,
+                                         const mgme::Workspace* wsp, hipStream_t stream);
 extern "C" hipError_t mgme_run_{name}_dc(int per_hel, dim3 grid, const double* mom, long long nevt, long long ld,
-                                          const mgme::MeArgs* args, double* out, long long ldo, hipStream_t stream);
+                                          const mgme::MeArgs* args, double* out, long long ldo,
+                                          const mgme::Workspace* wsp, hipStream_t stream);
+extern "C" hipError_t mgme_run_{name}_m(dim3 grid, const double* mom, long long nevt, long long ld,
+                                         const mgme::MeArgs* args, double* out, const mgme::Workspace* wsp,
+                                         hipStream_t stream);
 
 extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                           const mgme::MeArgs* args, double* out, long long ldo,
-                                          const mgme::SelectArgs* sel, hipStream_t stream) {{
+                                          const mgme::SelectArgs* sel, const mgme::Workspace* wsp,
+                                          hipStream_t stream) {{
   using namespace mgme::{name};
   const dim3 block(MGME_ME_BLOCK);
-  if (sel && prec != 2) return mgme_select_{name}(prec, mom, nevt, ld, args, out, sel, stream);
+  if (sel && prec != 2) return mgme_select_{name}(prec, mom, nevt, ld, args, out, sel, wsp, stream);
+  if (prec == 2 && !sel && !per_hel && NCOL <= 32) {{
+    // the colour sum on the matrix cores inside the diagram kernel
+    const dim3 grid((unsigned)((nevt + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
+    return mgme_run_{name}_m(grid, mom, nevt, ld, args, out, wsp, stream);
+  }}
   if (prec == 2) {{
     // single-precision diagrams write J, the matrix cores form the colour sum
     const int nh = args->nhel;
     const size_t per_event = (size_t)nh * (NCOL * sizeof(float2) + sizeof(double)) + (sel ? NCOL * sizeof(double) : 0);
-    long long sub = (long long)(((size_t)4 << 30) / per_event) / 64 * 64;
-    if (sub < 64) sub = 64;
-    if (sub > nevt) sub = (nevt + 63) / 64 * 64;
+    const long long sub = mgme::ws_sub_batch(wsp, per_event, (size_t)4 << 30, 0, nevt);
+    if (sub == 0) return hipErrorInvalidValue;
     char* ws = nullptr;
-    hipError_t err = hipMallocAsync((void**)&ws, per_event * (size_t)sub, stream);
+    hipError_t err = mgme::ws_acquire(wsp, per_event * (size_t)sub, (void**)&ws, stream);
     if (err != hipSuccess) return err;
     float2* J = (float2*)ws;
     double* meh = (double*)(ws + (size_t)nh * NCOL * sizeof(float2) * sub);
@@ -853,13 +887,13 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
         err = mgme::launch_jamp2<float>(n, nh, NCOL, (const float*)J, sub, jamp2, sub, stream);
       if (err == hipSuccess && sel) err = mgme::launch_select(n, args, meh, sub, NCOL, jamp2, sub, sel, start, stream);
     }}
-    const hipError_t ferr = hipFreeAsync(ws, stream);
+    const hipError_t ferr = mgme::ws_release(wsp, ws, stream);
     return err != hipSuccess ? err : ferr;
   }}
   const dim3 grid((unsigned)((nevt + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
-  if (prec == 0) return mgme_run_{name}_d(per_hel, grid, mom, nevt, ld, args, out, ldo, stream);
-  if (prec == 3) return mgme_run_{name}_dc(per_hel, grid, mom, nevt, ld, args, out, ldo, stream);
-  return mgme_run_{name}_f(per_hel, grid, mom, nevt, ld, args, out, ldo, stream);
+  if (prec == 0) return mgme_run_{name}_d(per_hel, grid, mom, nevt, ld, args, out, ldo, wsp, stream);
+  if (prec == 3) return mgme_run_{name}_dc(per_hel, grid, mom, nevt, ld, args, out, ldo, wsp, stream);
+  return mgme_run_{name}_f(per_hel, grid, mom, nevt, ld, args, out, ldo, wsp, stream);
 }}
 """
 
@@ -868,7 +902,7 @@ RUN_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: {wh
 
 extern "C" hipError_t mgme_run_{name}_{tag}(int per_hel, dim3 grid, const double* mom, long long nevt, long long ld,
                                              const mgme::MeArgs* args, double* out, long long ldo,
-                                             hipStream_t stream) {{
+                                             const mgme::Workspace* wsp, hipStream_t stream) {{
   using namespace mgme::{name};
   const dim3 block(MGME_ME_BLOCK);
   // a batch too small to fill the GPU spreads its helicity groups over grid.y
@@ -880,19 +914,52 @@ extern "C" hipError_t mgme_run_{name}_{tag}(int per_hel, dim3 grid, const double
                                                                                    nullptr, nullptr, 0);
     return hipGetLastError();
   }}
-  const int split = mgme::helicity_split((long long)grid.x * (MGME_ME_BLOCK / 64), ngroup);
+  const size_t part_bytes = sizeof(double) * (size_t)ngroup * (size_t)nevt;
+  int split = mgme::helicity_split((long long)grid.x * (MGME_ME_BLOCK / 64), ngroup);
+  // a caller's workspace too small for the group sums: one row (same bits)
+  if (wsp && wsp->ptr && part_bytes > (size_t)wsp->bytes) split = 1;
   if (split <= 1) {{
     me_kernel<{T}, 0, {TC}><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
     return hipGetLastError();
   }}
   double* part = nullptr;
-  hipError_t err = hipMallocAsync((void**)&part, sizeof(double) * (size_t)ngroup * (size_t)nevt, stream);
+  hipError_t err = mgme::ws_acquire(wsp, part_bytes, (void**)&part, stream);
   if (err != hipSuccess) return err;
   me_kernel<{T}, 0, {TC}><<<dim3(grid.x, (unsigned)split), block, 0, stream>>>(mom, nevt, ld, *args, out, ldo,
                                                                                nullptr, part, nevt);
   err = hipGetLastError();
   if (err == hipSuccess) err = mgme::launch_helicity_sum(nevt, ngroup, part, nevt, args->factor, out, stream);
-  const hipError_t ferr = hipFreeAsync(part, stream);
+  const hipError_t ferr = mgme::ws_release(wsp, part, stream);
+  return err != hipSuccess ? err : ferr;
+}}
+"""
+
+MIXED_RUN_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: FP32 diagrams with
+// the colour sum on the matrix cores in the same kernel.
+#include "me_{name}_kernel.h"
+
+extern "C" hipError_t mgme_run_{name}_m(dim3 grid, const double* mom, long long nevt, long long ld,
+                                         const mgme::MeArgs* args, double* out, const mgme::Workspace* wsp,
+                                         hipStream_t stream) {{
+  using namespace mgme::{name};
+  const dim3 block(MGME_ME_BLOCK);
+  // a batch too small to fill the GPU spreads its helicity groups over grid.y
+  const int ngroup = (args->nhel + MGME_HEL_GROUP - 1) / MGME_HEL_GROUP;
+  const size_t part_bytes = sizeof(double) * (size_t)ngroup * (size_t)nevt;
+  int split = mgme::helicity_split((long long)grid.x * (MGME_ME_BLOCK / 64), ngroup);
+  if (wsp && wsp->ptr && part_bytes > (size_t)wsp->bytes) split = 1;
+  if (split <= 1) {{
+    me_kernel<float, 4><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, 0, nullptr, nullptr, 0);
+    return hipGetLastError();
+  }}
+  double* part = nullptr;
+  hipError_t err = mgme::ws_acquire(wsp, part_bytes, (void**)&part, stream);
+  if (err != hipSuccess) return err;
+  me_kernel<float, 4><<<dim3(grid.x, (unsigned)split), block, 0, stream>>>(mom, nevt, ld, *args, out, 0, nullptr,
+                                                                           part, nevt);
+  err = hipGetLastError();
+  if (err == hipSuccess) err = mgme::launch_helicity_sum(nevt, ngroup, part, nevt, args->factor, out, stream);
+  const hipError_t ferr = mgme::ws_release(wsp, part, stream);
   return err != hipSuccess ? err : ferr;
 }}
 """
@@ -904,16 +971,15 @@ SELECT_TEMPLATE = r"""// Generated by paper_2303_18244_amd.codegen for {title}: 
 
 extern "C" hipError_t mgme_select_{name}(int prec, const double* mom, long long nevt, long long ld,
                                           const mgme::MeArgs* args, double* out, const mgme::SelectArgs* sel,
-                                          hipStream_t stream) {{
+                                          const mgme::Workspace* wsp, hipStream_t stream) {{
   using namespace mgme::{name};
   const dim3 block(MGME_ME_BLOCK);
   const int nh = args->nhel;
   const size_t per_event = (size_t)(nh + NCOL) * sizeof(double);
-  long long sub = (long long)(((size_t)4 << 30) / per_event) / 64 * 64;
-  if (sub < 64) sub = 64;
-  if (sub > nevt) sub = (nevt + 63) / 64 * 64;
+  const long long sub = mgme::ws_sub_batch(wsp, per_event, (size_t)4 << 30, 0, nevt);
+  if (sub == 0) return hipErrorInvalidValue;
   double* ws = nullptr;
-  hipError_t err = hipMallocAsync((void**)&ws, per_event * (size_t)sub, stream);
+  hipError_t err = mgme::ws_acquire(wsp, per_event * (size_t)sub, (void**)&ws, stream);
   if (err != hipSuccess) return err;
   for (long long start = 0; start < nevt && err == hipSuccess; start += sub) {{
     const long long n = (nevt - start < sub) ? nevt - start : sub;
@@ -929,7 +995,7 @@ extern "C" hipError_t mgme_select_{name}(int prec, const double* mom, long long 
     if (err == hipSuccess)
       err = mgme::launch_select(n, args, ws, sub, NCOL, ws + (size_t)nh * sub, sub, sel, start, stream);
   }}
-  const hipError_t ferr = hipFreeAsync(ws, stream);
+  const hipError_t ferr = mgme::ws_release(wsp, ws, stream);
   return err != hipSuccess ? err : ferr;
 }}
 """
@@ -947,6 +1013,7 @@ def kernel_sources(meta: Dict) -> Dict[str, str]:
                              ("f", "float", "double", "FP32 diagrams, FP64 colour sum"),
                              ("dc", "double", "float", "FP64 diagrams, FP32 colour algebra")):
         out[f"me_{name}_{tag}.hip"] = RUN_TEMPLATE.format(title=title, name=name, tag=tag, T=T, TC=TC, what=what)
+    out[f"me_{name}_m.hip"] = MIXED_RUN_TEMPLATE.format(title=title, name=name)
     return out
 
 
@@ -1069,24 +1136,23 @@ __global__ void __launch_bounds__(256) fold_kernel(long long nevt, const MeArgs 
 
 {chunk_decls}
 
-// Events are processed in sub-batches whose buffers fit the workspace bound;
-// the workspace comes from the stream-ordered allocator.
+// Events are processed in sub-batches whose buffers fit the workspace bound:
+// the caller's workspace when one is given, else {workspace_bytes} bytes
+// from the stream-ordered allocator.
 extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                           const mgme::MeArgs* args, double* out, long long ldo,
-                                          const mgme::SelectArgs* sel, hipStream_t stream) {{
+                                          const mgme::SelectArgs* sel, const mgme::Workspace* wsp,
+                                          hipStream_t stream) {{
   using namespace mgme::{name};
   const int nh = args->nhel;
   const int dprec = (prec == 0 || prec == 3) ? 0 : 1;  // diagram precision
   const size_t tsize = dprec == 0 ? sizeof(mgme::cx<double>) : sizeof(mgme::cx<float>);
   const size_t per_event = (size_t)nh * ((NCOL + NOV) * tsize + sizeof(double)) + (sel ? NCOL * sizeof(double) : 0);
-  const size_t budget = (size_t){workspace_bytes};
-  long long sub = (long long)(budget / per_event) / 64 * 64;
-  if (sub < 64) sub = 64;
-  if (sub > {max_sub}) sub = {max_sub};
-  if (sub > nevt) sub = (nevt + 63) / 64 * 64;
+  const long long sub = mgme::ws_sub_batch(wsp, per_event, (size_t){workspace_bytes}, {max_sub}, nevt);
+  if (sub == 0) return hipErrorInvalidValue;
   const size_t bytes = per_event * (size_t)sub;
   char* ws = nullptr;
-  hipError_t err = hipMallocAsync((void**)&ws, bytes, stream);
+  hipError_t err = mgme::ws_acquire(wsp, bytes, (void**)&ws, stream);
   if (err != hipSuccess) return err;
   void* Jbuf = ws;
   void* Ovbuf = ws + (size_t)nh * NCOL * tsize * sub;
@@ -1126,7 +1192,7 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
       if (err == hipSuccess) err = mgme::launch_select(n, args, meh, sub, NCOL, jamp2, sub, sel, start, stream);
     }}
   }}
-  const hipError_t ferr = hipFreeAsync(ws, stream);
+  const hipError_t ferr = mgme::ws_release(wsp, ws, stream);
   return err != hipSuccess ? err : ferr;
 }}
 """

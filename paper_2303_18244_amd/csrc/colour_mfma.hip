@@ -10,13 +10,22 @@
 // in [1/2, 1), then split into two half-precision parts, hi = fp16(x) and
 // lo = fp16(x - hi), so X is carried to about 2^-22 of its largest entry;
 // C's numerators (|c| <= 4096) are exact in half precision.  Products are
-// exact and accumulate in FP32; the result is rescaled and handed on in
-// double.  The relative error of me is bounded by about cond(C) 2^-22.
+// exact and accumulate in FP32; the final dot product X.Y, the rescaling and
+// the hand-over are in double.  The relative error of me is bounded by about
+// cond(C) 2^-22.
 //
 // Lane layout of the 32x32x16 f16 MFMA (gfx950): A[m][k] with m = lane%32,
 // k = 8 (lane/32) + j; B[k][n] with n = lane%32, k = 8 (lane/32) + j;
 // D[m][n] in result register i with n = lane%32,
 // m = 8 (i/4) + 4 (lane/32) + i%4.
+//
+// The rows of C in the A operand are permuted within each 32-row tile so
+// that result register i of a lane holds Y at a flow whose X the lane itself
+// supplied to the B operand: row r of the tile (in register
+// i = 4 (r/8) + r%4 of the lanes with lane/32 = (r/4)%2) carries flow
+// 16 (i/8) + 8 (lane/32) + i%8, which is B register j = i%8 of K step i/8 of
+// that tile.  The dot product X.Y then needs no data from other lanes and no
+// second read of J.
 #include <hip/hip_runtime.h>
 
 #include "colour_mfma.h"
@@ -56,7 +65,8 @@ __global__ void __launch_bounds__(256) colour_mfma_kernel(long long nevt, int nh
   mx = fmaxf(mx, __shfl_xor(mx, 32));
   int ex = 0;
   (void)frexpf(mx, &ex);
-  const float s = mx > 0.0f ? ldexpf(1.0f, -ex) : 1.0f;
+  // 2^-ex stays finite (mx below 2^-126 keeps the factor 2^126)
+  const float s = mx > 0.0f ? ldexpf(1.0f, ex < -126 ? 126 : -ex) : 1.0f;
   half8 rh[KS], rl[KS], ih[KS], il[KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks)
@@ -69,7 +79,8 @@ __global__ void __launch_bounds__(256) colour_mfma_kernel(long long nevt, int nh
       ih[ks][j] = bh;
       il[ks][j] = (_Float16)(b - (float)bh);
     }
-  float me = 0.0f;
+  static_assert(KS == 2 * MT, "two K steps per 32-row tile");
+  double me = 0.0;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     floatx16 dr = {}, di = {};
@@ -81,17 +92,18 @@ __global__ void __launch_bounds__(256) colour_mfma_kernel(long long nevt, int nh
       di = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, ih[ks], di, 0, 0, 0);
       di = __builtin_amdgcn_mfma_f32_32x32x16_f16(a, il[ks], di, 0, 0, 0);
     }
+    // register i holds Y at flow 32 mt + 16 (i/8) + 8 kh + i%8: the lane's
+    // own B entry j = i%8 of K step 2 mt + i/8 (hi + lo: the X of the GEMM)
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int m = 32 * mt + 8 * (i / 4) + 4 * kh + (i % 4);
-      if (valid && m < ncol) {
-        const float2 v = Jh[(long long)m * ldj + e];
-        me += v.x * s * dr[i] + v.y * s * di[i];
-      }
+      const int ks = 2 * mt + i / 8, j = i % 8;
+      const double xre = (double)(float)rh[ks][j] + (double)(float)rl[ks][j];
+      const double xim = (double)(float)ih[ks][j] + (double)(float)il[ks][j];
+      me += xre * (double)dr[i] + xim * (double)di[i];
     }
   }
   me += __shfl_xor(me, 32);
-  if (kh == 0 && valid) out[(long long)hs * ldo + e] = (double)me / ((double)s * (double)s) * scale;
+  if (kh == 0 && valid) out[(long long)hs * ldo + e] = me / ((double)s * (double)s) * scale;
 }
 
 int colour_mfma_tiles(int ncol, int* mt, int* ks) {
@@ -107,6 +119,14 @@ int colour_mfma_tiles(int ncol, int* mt, int* ks) {
   return 0;
 }
 
+// Flow carried by row r (0..31) of a 32-row tile of the A operand (see the
+// kernel's lane layout): register i = 4 (r/8) + r%4 of the lanes with
+// lane/32 = (r/4)%2 receives it.
+int colour_mfma_row_flow(int r) {
+  const int i = 4 * (r / 8) + r % 4, kh = (r / 4) % 2;
+  return 16 * (i / 8) + 8 * kh + i % 8;
+}
+
 void colour_mfma_fragments(int ncol, const long long* num, unsigned short* frag_half_bits) {
   int MT = 0, KS = 0;
   colour_mfma_tiles(ncol, &MT, &KS);
@@ -114,7 +134,7 @@ void colour_mfma_fragments(int ncol, const long long* num, unsigned short* frag_
     for (int ks = 0; ks < KS; ++ks)
       for (int lane = 0; lane < 64; ++lane)
         for (int j = 0; j < 8; ++j) {
-          const int m = 32 * mt + lane % 32, k = 16 * ks + 8 * (lane / 32) + j;
+          const int m = 32 * mt + colour_mfma_row_flow(lane % 32), k = 16 * ks + 8 * (lane / 32) + j;
           const float c = (m < ncol && k < ncol) ? (float)num[(size_t)m * ncol + k] : 0.0f;
           const _Float16 h = (_Float16)c;
           unsigned short bits;

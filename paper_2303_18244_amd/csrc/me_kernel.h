@@ -38,13 +38,49 @@ struct SelectArgs {
   int* col;             // chosen colour flow (basis index)
 };
 
+// Device workspace of one launch: a buffer the caller provides (its size then
+// bounds the sub-batches, and nothing is allocated), or, when ptr is NULL,
+// memory from the stream-ordered allocator returned at the end of the launch.
+struct Workspace {
+  void* ptr;
+  long long bytes;
+};
+
+// Events per sub-batch for per_event bytes of workspace per event: bounded by
+// the caller's buffer when one is given, else by `cap` bytes; at most max_sub
+// (when > 0) and at most nevt rounded up to 64.  0 when a caller's buffer
+// cannot hold 64 events.
+inline long long ws_sub_batch(const Workspace* ws, size_t per_event, size_t cap, long long max_sub, long long nevt) {
+  const bool given = ws && ws->ptr;
+  long long sub = (long long)((given ? (size_t)ws->bytes : cap) / per_event) / 64 * 64;
+  if (sub < 64) {
+    if (given) return 0;
+    sub = 64;
+  }
+  if (max_sub > 0 && sub > max_sub) sub = max_sub;
+  const long long whole = (nevt + 63) / 64 * 64;
+  return sub < whole ? sub : whole;
+}
+
+inline hipError_t ws_acquire(const Workspace* ws, size_t bytes, void** p, hipStream_t stream) {
+  if (ws && ws->ptr) {
+    *p = ws->ptr;
+    return bytes <= (size_t)ws->bytes ? hipSuccess : hipErrorInvalidValue;
+  }
+  return hipMallocAsync(p, bytes, stream);
+}
+
+inline hipError_t ws_release(const Workspace* ws, void* p, hipStream_t stream) {
+  return (ws && ws->ptr) ? hipSuccess : hipFreeAsync(p, stream);
+}
+
 // prec: 0 FP64, 1 FP32 diagrams, 2 FP32 diagrams + 16-bit matrix-core colour sum,
 // 3 FP64 diagrams + FP32 colour algebra.  per_hel: per-helicity output with
 // leading dimension ldo.  sel: when not NULL, also choose a helicity and a
-// colour flow per event (per_hel must be 0).
+// colour flow per event (per_hel must be 0).  ws: caller's workspace, or NULL.
 using LaunchFn = hipError_t (*)(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                 const MeArgs* args, double* out, long long ldo, const SelectArgs* sel,
-                                hipStream_t stream);
+                                const Workspace* ws, hipStream_t stream);
 
 // Number of grid rows over which a fused kernel spreads its ngroup helicity
 // groups when `waves` waves of 64 events would leave the GPU underfilled

@@ -16,6 +16,7 @@
 #include "me_kernel.h"
 #include "rambo.h"
 #include "events.h"
+#include "internal.h"
 #include "registry.h"
 
 struct mgme_process {
@@ -116,7 +117,7 @@ int calibrate(mgme_process* p) {
   for (int i = 0; i < nhel; ++i) all.hel[i] = i;
   rc = launch_rambo_checked(p, sqrt_s, 1ull, 0ull, nev, nev, d_mom, nullptr, nullptr);
   if (rc == MGME_OK) {
-    e = p->entry->launch(0, 1, d_mom, nev, nev, &all, d_out, nev, nullptr, nullptr);
+    e = p->entry->launch(0, 1, d_mom, nev, nev, &all, d_out, nev, nullptr, nullptr, nullptr);
     if (e != hipSuccess) rc = hip_fail(e, "calibration launch");
   }
   if (rc == MGME_OK) {
@@ -173,6 +174,19 @@ int helicity_split(long long waves, int ngroup) {
   return (int)(s < ngroup ? s : ngroup);
 }
 
+// Staging bytes per event of a launch (0: none), as the generated launchers
+// lay them out without the helicity and colour choice.  The fused processes
+// (at most 32 flows) form the mixed-precision colour sum inside the diagram
+// kernel and stage nothing.
+long long staging_per_event(const ProcEntry& e, int nhel, int prec) {
+  if (e.staged) {
+    const long long tsize = (prec == MGME_FP64 || prec == MGME_FP64_FP32COLOUR) ? 16 : 8;
+    return (long long)nhel * ((e.n_colour + e.n_overflow) * tsize + 8);
+  }
+  if (prec == MGME_MIXED && e.n_colour > 32) return (long long)nhel * (e.n_colour * 8 + 8);
+  return 0;
+}
+
 // Workspace bounds of the generated launchers: staged processes take up to
 // 12 GB (at most 16384 events per sub-batch), the mixed-precision path of the
 // other processes up to 4 GB.
@@ -180,16 +194,15 @@ long long workspace_bytes(const ProcEntry& e, int nhel, long long nevt, int prec
   if (nevt <= 0) return 0;
   const long long round64 = (nevt + 63) / 64 * 64;
   if (e.staged) {
-    const long long tsize = (prec == MGME_FP64 || prec == MGME_FP64_FP32COLOUR) ? 16 : 8;
-    const long long per_event = (long long)nhel * ((e.n_colour + e.n_overflow) * tsize + 8);
+    const long long per_event = staging_per_event(e, nhel, prec);
     long long sub = (12ll << 30) / per_event / 64 * 64;
     if (sub < 64) sub = 64;
     if (sub > 16384) sub = 16384;
     if (sub > round64) sub = round64;
     return per_event * sub;
   }
-  if (prec == 2) {
-    const long long per_event = (long long)nhel * (e.n_colour * 8 + 8);
+  if (prec == MGME_MIXED && e.n_colour > 32) {
+    const long long per_event = staging_per_event(e, nhel, prec);
     long long sub = (4ll << 30) / per_event / 64 * 64;
     if (sub < 64) sub = 64;
     if (sub > round64) sub = round64;
@@ -201,6 +214,31 @@ long long workspace_bytes(const ProcEntry& e, int nhel, long long nevt, int prec
   const long long waves = (nevt + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK * (MGME_ME_BLOCK / 64);
   if (helicity_split(waves, ngroup) > 1) return 8LL * ngroup * nevt;
   return 0;
+}
+
+long long workspace_min_bytes(const mgme_process* proc, int precision) {
+  return 64 * staging_per_event(*proc->entry, proc->args.nhel, precision);
+}
+
+int process_device(const mgme_process* proc) { return proc->device; }
+
+int process_n_ext(const mgme_process* proc) { return proc->entry->n_ext; }
+
+int set_error(int code, const char* msg) { return fail(code, msg); }
+
+int matrix_element_ws(const mgme_process* proc, const double* d_mom, long long nevt, long long ld, int precision,
+                      double* d_me, const Workspace* ws, hipStream_t stream) {
+  int rc = check_batch(proc, d_mom, d_me, nevt, ld);
+  if (rc != MGME_OK) return rc;
+  if (!valid_precision(precision)) return fail(MGME_EINVAL, "unknown precision");
+  if (ws && ws->ptr && ws->bytes < workspace_min_bytes(proc, precision))
+    return fail(MGME_EINVAL, "workspace smaller than one 64-event sub-batch of the staging buffers");
+  if ((rc = check_pending("mgme_matrix_element")) != MGME_OK) return rc;
+  if (nevt == 0) return MGME_OK;
+  if ((rc = select_device(proc->device)) != MGME_OK) return rc;
+  const hipError_t e = proc->entry->launch(precision, 0, d_mom, nevt, ld, &proc->args, d_me, 0, nullptr, ws, stream);
+  if (e != hipSuccess) return hip_fail(e, "matrix element launch");
+  return MGME_OK;
 }
 
 }  // namespace mgme
@@ -360,16 +398,7 @@ int mgme_rambo(const mgme_process* proc, double sqrt_s, unsigned long long seed,
 
 int mgme_matrix_element(const mgme_process* proc, const double* d_mom, long long nevt, long long ld, int precision,
                         double* d_me, void* hip_stream) {
-  int rc = check_batch(proc, d_mom, d_me, nevt, ld);
-  if (rc != MGME_OK) return rc;
-  if (!valid_precision(precision)) return fail(MGME_EINVAL, "unknown precision");
-  if ((rc = check_pending("mgme_matrix_element")) != MGME_OK) return rc;
-  if (nevt == 0) return MGME_OK;
-  if ((rc = select_device(proc->device)) != MGME_OK) return rc;
-  const hipError_t e =
-      proc->entry->launch(precision, 0, d_mom, nevt, ld, &proc->args, d_me, 0, nullptr, (hipStream_t)hip_stream);
-  if (e != hipSuccess) return hip_fail(e, "matrix element launch");
-  return MGME_OK;
+  return mgme::matrix_element_ws(proc, d_mom, nevt, ld, precision, d_me, nullptr, (hipStream_t)hip_stream);
 }
 
 int mgme_matrix_element_per_helicity(const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
@@ -385,7 +414,7 @@ int mgme_matrix_element_per_helicity(const mgme_process* proc, const double* d_m
   all.nhel = 1 << proc->entry->n_ext;
   for (int i = 0; i < all.nhel; ++i) all.hel[i] = i;
   const hipError_t e =
-      proc->entry->launch(precision, 1, d_mom, nevt, ld, &all, d_out, ldo, nullptr, (hipStream_t)hip_stream);
+      proc->entry->launch(precision, 1, d_mom, nevt, ld, &all, d_out, ldo, nullptr, nullptr, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "matrix element launch");
   return MGME_OK;
 }
@@ -402,7 +431,7 @@ int mgme_select(const mgme_process* proc, const double* d_mom, long long nevt, l
   if ((rc = select_device(proc->device)) != MGME_OK) return rc;
   const mgme::SelectArgs sel{d_r_hel, d_r_col, d_hel, d_col};
   const hipError_t e =
-      proc->entry->launch(precision, 0, d_mom, nevt, ld, &proc->args, d_me, 0, &sel, (hipStream_t)hip_stream);
+      proc->entry->launch(precision, 0, d_mom, nevt, ld, &proc->args, d_me, 0, &sel, nullptr, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "matrix element launch");
   return MGME_OK;
 }

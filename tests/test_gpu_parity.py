@@ -1,7 +1,8 @@
 """GPU parity of the HIP path (through the C ABI) against the oracle.
 
 Tolerances: FP64 |M|^2 per event within 1e-12 relative (an event outside it
-is re-evaluated by the long-double oracle and must be within 1e-12 of that);
+is re-evaluated by the long-double oracle and must be within 1e-12 of that,
+or within 512 u kappa with kappa the event's condition number: fp64_check.py);
 FP32 diagrams: the batch mean and the per-event median within 1e-5
 relative (the paper's cross-section criterion for reduced precision),
 per-event p99 and maximum printed.  RAMBO momenta within 1e-12 sqrt(s):
@@ -13,6 +14,7 @@ import os
 
 import numpy as np
 import pytest
+from fp64_check import check
 
 pytestmark = pytest.mark.gpu
 
@@ -91,14 +93,13 @@ def _masses(pdg):
     return [173.0 if abs(x) == 6 else 0.0 for x in pdg[2:]]
 
 
-def _check_fp64(gpu, mom_host, oproc, tol=1e-12):
+def _check_fp64(gpu, mom_host, oproc):
+    """The rule of fp64_check.py: per event within 1e-12 of the oracle's
+    double value, or, for an ill-conditioned event, within 512 u kappa of the
+    long-double oracle (both evaluated for the outliers only)."""
     ref = oproc.me(mom_host, nthreads=NTHREADS)
-    rel = np.abs(gpu / ref - 1.0)
-    bad = np.nonzero(rel > tol)[0]
-    if len(bad):
-        ld = oproc.me(mom_host[bad], precision=1, nthreads=NTHREADS)
-        rel_ld = np.abs(gpu[bad] / ld - 1.0)
-        assert np.all(rel_ld <= tol), (bad[:10], rel[bad][:10], rel_ld[:10])
+    rel, _, _ = check(gpu, ref, lambda idx: oproc.me(mom_host[idx], precision=1, nthreads=NTHREADS),
+                      lambda idx: np.array([oproc.condition(mom_host[i]) for i in idx]))
     return rel
 
 
@@ -293,9 +294,10 @@ def test_determinism_and_ragged_edges(lib_procs):
 @pytest.mark.parametrize("name", ["gg_ttgg", "gg_ttggg"])
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_staging_edges(lib_procs, name, prec):
-    """Ragged batch sizes, a padded leading dimension and batches spanning
-    several sub-batches of the staging buffers give the same per-event values
-    as one small batch."""
+    """Ragged batch sizes and a padded leading dimension give the same
+    per-event values as one small batch; for the staged process a batch of
+    16684 events spans two 16384-event sub-batches of the staging buffers,
+    and the events on both sides of the boundary equal a small batch's."""
     torch = _torch()
     P = _proc(lib_procs, name)
     n = 200
@@ -304,6 +306,13 @@ def test_staging_edges(lib_procs, name, prec):
     for m in (1, 63, 65, 131):
         b = P.matrix_element(mom[:, :, :m].contiguous(), precision=prec).cpu().numpy()
         np.testing.assert_array_equal(b, a[:m])
+    if name == "gg_ttggg":
+        big, _ = P.rambo(1500.0, SEED, 0, 16384 + 300)
+        whole = P.matrix_element(big, precision=prec).cpu().numpy()
+        np.testing.assert_array_equal(whole[:n], a)
+        edge = P.matrix_element(big[:, :, 16300:].contiguous(), precision=prec).cpu().numpy()
+        np.testing.assert_array_equal(whole[16300:], edge)
+        assert np.all(np.isfinite(whole)) and np.all(whole > 0)
     padded = torch.zeros((P.n_ext, 4, 256), dtype=torch.float64, device="cuda")
     padded[:, :, :n] = mom
     out = torch.full((256,), -5.0, dtype=torch.float64, device="cuda")

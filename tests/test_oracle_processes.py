@@ -379,3 +379,61 @@ def test_soft_gluon_limit(procs, oracle_mod, hard_name, soft_leg, delta, tol, n_
                 assert abs(J[s] - pred) <= tol * abs(eik) * scale * gs, (h, lam, order, J[s], pred)
                 checked += 1
     assert checked >= 2 * len(hels) * len(basis_s)
+
+
+# ------------------------------------------------ condition number of |M|^2
+def test_condition_ee_closed_form(procs, oracle_mod):
+    """e+e- -> mu+mu-: per helicity one photon and one Z diagram, so
+    kappa = sum_ij X_ij (|A_gamma| + |A_Z,ij|)^2 / sum_ij X_ij |A_ij|^2 with
+    X = u^2 for equal and t^2 for opposite lepton helicities; the photon alone
+    has kappa = 1."""
+    mom = two_body(50, 500.0, 0.0)
+    s = 500.0 ** 2
+    cw2 = 1 - SW2
+    gl, gr = -0.5 + SW2, SW2
+    D = s - MZ ** 2 + 1j * MZ * WZ
+    A = ee_amplitudes(s)
+    za = lambda gi, gj: abs(gi * gj / (SW2 * cw2 * D))
+    P0 = oracle_mod.Process(oracle_mod.PROCESSES["ee_mumu"], z_enabled=0)
+    for p in mom:
+        t = -2 * mdot(p[0], p[2])
+        u = -2 * mdot(p[0], p[3])
+        num = (u ** 2 * ((1 / s + za(gl, gl)) ** 2 + (1 / s + za(gr, gr)) ** 2)
+               + t ** 2 * ((1 / s + za(gl, gr)) ** 2 + (1 / s + za(gr, gl)) ** 2))
+        den = (u ** 2 * (abs(A["LL"]) ** 2 + abs(A["RR"]) ** 2) + t ** 2 * (abs(A["LR"]) ** 2 + abs(A["RL"]) ** 2))
+        assert procs["ee_mumu"].condition(p) == pytest.approx(num / den, rel=1e-13)
+        assert P0.condition(p) == pytest.approx(1.0, rel=1e-15)
+
+
+@pytest.mark.parametrize("name,n", [("gg_tt", 50), ("gg_ttg", 20), ("gg_ttgg", 4)])
+def test_condition_invariances(procs, oracle_mod, name, n):
+    """kappa >= 1 (triangle inequality); independent of alpha_s (every
+    diagram carries the same power of g_s); unchanged when two final-state
+    gluons are exchanged (the amplitudes are permuted)."""
+    mom, _ = events(oracle_mod, name, n)
+    P = procs[name]
+    P2 = oracle_mod.Process(oracle_mod.PROCESSES[name], alpha_s=0.2)
+    for p in mom:
+        k = P.condition(p)
+        assert k >= 1.0 - 1e-15
+        assert P2.condition(p) == pytest.approx(k, rel=1e-13)
+        if P.n_ext >= 6:
+            q = p.copy()
+            q[[4, 5]] = p[[5, 4]]
+            assert P.condition(q) == pytest.approx(k, rel=1e-12)
+
+
+def test_condition_bounds_fp64_rounding(procs, oracle_mod):
+    """The bound the GPU parity tests use for ill-conditioned events holds
+    for the oracle's own FP64 evaluation: |double / long double - 1| is
+    within 512 u kappa on the worst-rounded events of a sample."""
+    P = procs["gg_ttgg"]
+    mom, _ = events(oracle_mod, "gg_ttgg", 1500)
+    d = P.me(mom, nthreads=8)
+    ld = P.me(mom, precision=1, nthreads=8)
+    rel = np.abs(d / ld - 1.0)
+    u = 2.0 ** -53
+    idx = np.argsort(rel)[-20:]  # the worst-rounded events
+    for i in idx:
+        k = P.condition(mom[i])
+        assert rel[i] <= 512 * u * k, (i, rel[i], k)

@@ -1,44 +1,152 @@
 """Serving loop on the GPU: requests of different processes, sizes and
-precisions run concurrently, and each result equals the same request run
-alone (bitwise: every request runs the kernels of a standalone call)."""
+precisions run concurrently, with and without graph-captured launches; each
+result equals the same request run alone (bitwise: every request runs the
+kernels of a standalone call), and the FP64 requests of the benchmark event
+stream equal the oracle's |M|^2 stored in tests/golden (1e-12 relative, with
+the rule of fp64_check.py for ill-conditioned events)."""
+import os
+
 import numpy as np
 import pytest
+from fp64_check import check
 
 pytestmark = pytest.mark.gpu
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden")
+SEED = 230318244
 
-def test_mix_equals_alone():
+PLAN = [("gg_tt", 5000, 0), ("gg_ttgg", 3000, 2), ("gg_ttggg", 300, 0), ("gg_ttg", 20000, 1),
+        ("gg_ttgg", 7001, 0), ("gg_ttggg", 197, 2), ("ee_mumu", 4000, 0), ("gg_ttg", 1500, 2),
+        ("gg_tt", 65536, 1), ("gg_ttgg", 1024, 1), ("gg_ttgg", 2000, 3), ("gg_ttggg", 700, 3),
+        ("gg_ttgg", 3000, 0), ("gg_ttggg", 300, 0), ("gg_ttg", 1500, 0)]
+
+
+def _setup():
     import torch
 
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_2303_18244_amd as M
 
-    procs = {name: M.Process(pdg) for name, pdg in M.PROCESSES.items()}
-    plan = [("gg_tt", 5000, M.FP64), ("gg_ttgg", 3000, M.MIXED), ("gg_ttggg", 300, M.FP64),
-            ("gg_ttg", 20000, M.FP32), ("gg_ttgg", 7001, M.FP64), ("gg_ttggg", 197, M.MIXED),
-            ("ee_mumu", 4000, M.FP64), ("gg_ttg", 1500, M.MIXED), ("gg_tt", 65536, M.FP32),
-            ("gg_ttgg", 1024, M.FP32), ("gg_ttgg", 2000, M.FP64_FP32COLOUR)]
-    inputs, refs = [], []
-    for k, (name, n, prec) in enumerate(plan):
+    return torch, M
+
+
+@pytest.fixture(scope="module")
+def procs():
+    torch, M = _setup()
+    return {name: M.Process(pdg) for name, pdg in M.PROCESSES.items()}
+
+
+def _golden_request(name, prec):
+    return prec == 0 and name in ("gg_ttgg", "gg_ttggg")
+
+
+def _inputs(torch, procs, oracle_mod):
+    inputs, refs, hosts = [], [], {}
+    for k, (name, n, prec) in enumerate(PLAN):
         P = procs[name]
         sq = 500.0 if name == "ee_mumu" else 1500.0
-        mom, _ = P.rambo(sq, 1000 + k, 0, n)
+        if _golden_request(name, prec):
+            # the oracle's own RAMBO events of the benchmark stream, whose
+            # |M|^2 the oracle stored in tests/golden
+            masses = [173.0 if abs(x) == 6 else 0.0 for x in P.pdg[2:]]
+            host, _ = oracle_mod.rambo(masses, sq, SEED, 0, n)
+            if name not in hosts or len(hosts[name]) < n:
+                hosts[name] = host
+            mom = torch.from_numpy(np.ascontiguousarray(host.transpose(1, 2, 0))).to("cuda")
+        else:
+            mom, _ = P.rambo(sq, 1000 + k, 0, n)
         inputs.append(mom)
         refs.append(P.matrix_element(mom, precision=prec).clone())
     torch.cuda.synchronize()
-    S = M.Server(n_slots=4, hbm_budget_bytes=24 << 30)
+    return inputs, refs, hosts
+
+
+def _golden(name):
+    """[n, 2]: the oracle's |M|^2 in double and in long double."""
+    path = {"gg_ttgg": "oracle_me_gg_ttgg_65536.npy", "gg_ttggg": "oracle_me_gg_ttggg_8192.npy"}[name]
+    f = os.path.join(GOLDEN, path)
+    return np.load(f) if os.path.exists(f) else None
+
+
+@pytest.mark.parametrize("use_graphs", [False, True])
+def test_mix_equals_alone_and_oracle(procs, oracle_mod, use_graphs):
+    torch, M = _setup()
+    print(f"serving mix, graphs={use_graphs}", flush=True)
+    inputs, refs, hosts = _inputs(torch, procs, oracle_mod)
+    S = M.Server(n_slots=4, use_graphs=use_graphs)
     outs, ids = [], []
-    for (name, n, prec), mom in zip(plan, inputs):
+    for (name, n, prec), mom in zip(PLAN, inputs):
+        # the output is initialised on torch's stream just before submission:
+        # the request's kernels wait for it (readiness event)
         out = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
         outs.append(out)
         ids.append(S.submit(procs[name], mom, precision=prec, out=out))
-    lat = [S.wait(i) for i in ids]
+    [S.wait(i) for i in ids]
     st = S.stats()
     S.close()
-    assert st["completed"] == len(plan) and st["failed"] == 0
-    assert st["max_concurrent"] >= 2
-    for (name, n, prec), out, ref in zip(plan, outs, refs):
+    assert st["completed"] == len(PLAN) and st["failed"] == 0
+    assert st["max_concurrent"] >= 2 and st["budget_bytes"] > 0
+    if use_graphs:
+        assert st["graph_launches"] == len(PLAN)
+        # requests of the same process, precision and size bucket on one slot reuse its graph
+        assert st["graph_instantiations"] <= len(PLAN)
+    for (name, n, prec), out, ref in zip(PLAN, outs, refs):
         assert torch.equal(out, ref), (name, n, prec)
-    print(f"served {len(plan)} requests, latency p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms, "
-          f"max concurrent {st['max_concurrent']}")
+    checked = 0
+    for (name, n, prec), out in zip(PLAN, outs):
+        if not _golden_request(name, prec):
+            continue
+        g = _golden(name)
+        if g is None:
+            continue
+        O = oracle_mod.Process(oracle_mod.PROCESSES[name])
+        host = hosts[name]
+        check(out.cpu().numpy(), g[:n, 0], g[:n, 1], lambda idx: np.array([O.condition(host[i]) for i in idx]))
+        checked += 1
+    assert checked >= 2
+    print(f"served {len(PLAN)} requests (graphs={use_graphs}): p50 {st['p50_ms']:.2f} ms, "
+          f"p99 {st['p99_ms']:.2f} ms, max concurrent {st['max_concurrent']}, "
+          f"graphs launched {st['graph_launches']}, instantiated {st['graph_instantiations']}; "
+          f"{checked} FP64 requests equal the oracle's stored values")
+
+
+def test_graph_replays_with_eager_work_between(procs):
+    """One slot, the same kind of request replayed through its graph several
+    times (updated in place for a new size and new buffers), with eager work
+    and synchronisations of the program between the replays: every replay
+    equals the eager call."""
+    torch, M = _setup()
+    P = procs["gg_ttggg"]
+    S = M.Server(n_slots=1, use_graphs=True, slot_workspace_bytes=256 << 20)
+    for k, n in enumerate([300, 400, 290, 511, 300]):
+        mom, _ = P.rambo(1500.0, 77 + k, 0, n)
+        ref = P.matrix_element(mom, precision=M.FP64)
+        torch.cuda.synchronize()
+        out = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
+        S.wait(S.submit(P, mom, precision=M.FP64, out=out))
+        _ = (mom * 2.0).sum().item()  # eager work between replays
+        assert torch.equal(out, ref), (k, n)
+    st = S.stats()
+    S.close()
+    assert st["graph_launches"] == 5 and st["graph_instantiations"] <= 2
+
+
+def test_oversize_request_is_split_on_the_device(procs):
+    """A request larger than the budget runs as parts that fit; its result
+    equals the standalone call."""
+    torch, M = _setup()
+    P = procs["gg_ttgg"]
+    n = 20000
+    mom, _ = P.rambo(1500.0, 5, 0, n)
+    ref = P.matrix_element(mom, precision=M.FP64)
+    torch.cuda.synchronize()
+    # momenta, result and group sums take 264 bytes per event: 1 MB holds parts of 2560 events
+    S = M.Server(n_slots=2, hbm_budget_bytes=1_000_000)
+    out = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
+    S.wait(S.submit(P, mom, precision=M.FP64, out=out))
+    st = S.stats()
+    S.close()
+    assert st["split_requests"] == 1 and st["peak_footprint_bytes"] <= 1_000_000
+    assert torch.equal(out, ref)
