@@ -135,6 +135,26 @@ int mgme_rambo(const mgme_process* proc, double sqrt_s, unsigned long long seed,
 int mgme_matrix_element(const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
                         int precision, double* d_me, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * mgme_matrix_element with the same arguments, results (bit for bit) and
+ * errors, but no device allocation of any kind.  Its staging buffers live in
+ * a fixed array of MGME_NOALLOC_SCRATCH_BYTES in the library, one per GPU,
+ * held until the process ends; its address is looked up on the first call on
+ * each device.  Batches of any size are processed in sub-batches that fit the
+ * array (g g -> t t~ g g g: 512 events per sub-batch in FP64, 1024 in FP32
+ * and mixed), so large staged batches run slower than with
+ * mgme_matrix_element.  The array keeps the contents of the last call; no
+ * kernel relies on it starting at zero.  Every call on one GPU shares the
+ * array: calls that overlap on one GPU (on different streams, or from
+ * different threads without ordering) race, and the caller must serialise
+ * them, for example by issuing them on one stream.
+ * Errors: as mgme_matrix_element, and EINVAL when one 64-event sub-batch of
+ * the process and precision would need more than the array. */
+#define MGME_NOALLOC_SCRATCH_BYTES (128ll << 20)
+int mgme_matrix_element_noalloc(const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
+                                int precision, double* d_me, void* hip_stream);
+
 /* Device workspace (bytes) that mgme_matrix_element takes from the
  * stream-ordered allocator for a batch of nevt events in `precision`
  * (0 when the process needs none). */

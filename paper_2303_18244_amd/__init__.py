@@ -30,7 +30,8 @@ DEFAULT_PARAMS = dict(alpha_s=0.118, alpha_em=1.0 / 132.5, sin2w=0.2222, mz=91.1
 
 # Entry points declared in include/mgme.h.
 EXPORTS = ["mgme_process_create", "mgme_process_destroy", "mgme_process_info", "mgme_good_helicities",
-           "mgme_colour_matrix", "mgme_rambo", "mgme_matrix_element", "mgme_matrix_element_per_helicity",
+           "mgme_colour_matrix", "mgme_rambo", "mgme_matrix_element", "mgme_matrix_element_noalloc",
+           "mgme_matrix_element_per_helicity",
            "mgme_workspace_bytes", "mgme_select", "mgme_event_weights", "mgme_unweight",
            "mgme_last_error", "mgme_server_create", "mgme_server_submit",
            "mgme_server_wait", "mgme_server_drain", "mgme_server_get_stats", "mgme_server_destroy",
@@ -99,6 +100,7 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(ctypes.c_int)]
         L.mgme_rambo.argtypes = [vp, ctypes.c_double, u64, u64, i64, i64, dp, dp, vp]
         L.mgme_matrix_element.argtypes = [vp, dp, i64, i64, ctypes.c_int, dp, vp]
+        L.mgme_matrix_element_noalloc.argtypes = [vp, dp, i64, i64, ctypes.c_int, dp, vp]
         L.mgme_matrix_element_per_helicity.argtypes = [vp, dp, i64, i64, ctypes.c_int, dp, i64, vp]
         L.mgme_workspace_bytes.argtypes = [vp, i64, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
         L.mgme_select.argtypes = [vp, dp, i64, i64, ctypes.c_int, dp, dp, dp, vp, vp, vp]
@@ -207,6 +209,21 @@ class Process:
             out = torch.empty(max(nevt, 1), dtype=torch.float64, device=mom.device)
         _check(lib().mgme_matrix_element(self._h, mom.data_ptr(), int(nevt), int(ld), int(precision),
                                          out.data_ptr(), _stream_handle(stream)))
+        return out[:nevt]
+
+    def matrix_element_noalloc(self, mom, nevt: Optional[int] = None, precision: int = FP64, out=None,
+                               stream=None):
+        """As matrix_element, through mgme_matrix_element_noalloc (no device
+        allocation inside the call; `out` should then be given)."""
+        import torch
+        ld = mom.shape[-1]
+        nevt = ld if nevt is None else nevt
+        if mom.dtype != torch.float64 or not mom.is_contiguous() or mom.shape[:2] != (self.n_ext, 4):
+            raise MgmeError(MGME_EINVAL, "momenta must be a contiguous float64 tensor [n_ext, 4, ld]")
+        if out is None:
+            out = torch.empty(max(nevt, 1), dtype=torch.float64, device=mom.device)
+        _check(lib().mgme_matrix_element_noalloc(self._h, mom.data_ptr(), int(nevt), int(ld), int(precision),
+                                                 out.data_ptr(), _stream_handle(stream)))
         return out[:nevt]
 
     def matrix_element_per_helicity(self, mom, nevt: Optional[int] = None, precision: int = FP64, stream=None):
