@@ -143,6 +143,12 @@ class GGBody:
         # (distance-2 pipelining only); the denominators are then loaded
         # instead of recomputed for every helicity
         self.den_index: Optional[Dict[tuple, int]] = None
+        # kin_index: momentum mask -> row of the per-event table `skin` (T[4]
+        # sums, shared by the lanes of one event); with it the denominators
+        # come from a T table `sden` too, and a call's values are loaded two
+        # calls ahead straight into its own registers (no sums in the loop)
+        self.kin_index: Optional[Dict[int, int]] = None
+        self.kin_split = False  # one load per component (load_kin_lds1)
         self.calls: List[Optional[tuple]] = []  # per routine call: its momentum needs
         if prefetch:
             em.w("@@PFHEAD@@")
@@ -159,6 +165,11 @@ class GGBody:
         return i, f"@@PF{i}@@"
 
     def pf_decl(self, j: int) -> str:
+        if self.kin_index is not None and self.pf_dist == 2:
+            return ""  # declared with the loads, two calls ahead
+        return self._vec_decl(j)
+
+    def _vec_decl(self, j: int) -> str:
         needs = self.calls[j] if j < len(self.calls) else None
         if needs is None:
             return ""
@@ -171,6 +182,8 @@ class GGBody:
 
     def pf_code(self, j: int) -> str:
         needs = self.calls[j] if j < len(self.calls) else None
+        if needs is not None and self.kin_index is not None:
+            return self.kin_loads(j)
         return "" if needs is None else self.pf_code_split(j, needs)
 
     def _union(self, j: int) -> int:
@@ -202,8 +215,26 @@ class GGBody:
             return 0
         return self._union(j)
 
+    def kin_loads(self, j: int) -> str:
+        """Distance 2 with the kinematics table: call j's momentum sums and
+        denominator loaded from the event's rows."""
+        needs = self.calls[j] if j < len(self.calls) else None
+        if needs is None:
+            return ""
+        kind, masks = needs[0], [m for m in needs[1:] if isinstance(m, int)]
+        names = {"vvv": ["k1", "k2"], "prop": ["P"], "den": [], "amp3": ["k1", "k2", "k3"]}[kind]
+        fn = "load_kin_lds1" if self.kin_split else "load_kin_lds"
+        out = "".join(f"{fn}<T, {self.mom_block}>(pf{j}_{v}, skin, {self.kin_index[m]}, lane); "
+                      for v, m in zip(names, masks))
+        k = self.den_key(needs)
+        if k is not None:
+            out += f"pf{j}_den = load_tden_lds<T, {self.mom_block}>(sden, {self.den_index[k]}, lane); "
+        return out + "pf_barrier<T>(); "
+
     def pf_loads(self, j: int) -> str:
         """Distance 2: the LDS loads of call j into its raw registers."""
+        if self.kin_index is not None:
+            return self.kin_loads(j)
         u = self._legs(j)
         out = ""
         if u:
@@ -215,6 +246,8 @@ class GGBody:
 
     def pf_raw_decl(self, j: int) -> str:
         """Declarations of the raw registers that call j's loads fill."""
+        if self.kin_index is not None:
+            return self._vec_decl(j)
         parts = []
         if self._legs(j):
             parts.append(f"double pf{j}_r[NEXT][4];")
@@ -225,7 +258,7 @@ class GGBody:
     def pf_sums(self, j: int) -> str:
         """Distance 2: sums and denominator of call j from its raw registers."""
         needs = self.calls[j] if j < len(self.calls) else None
-        if needs is None:
+        if needs is None or self.kin_index is not None:
             return ""
         return "{ " + self.pf_arith(j, needs, f"pf{j}_r")
 
@@ -289,22 +322,23 @@ class GGBody:
                 out.append(ln)
             self.em.lines = out
             return
+        ahead = self.pf_dist  # 1, or 0: each call loads its own values at its start
         for ln in self.em.lines:
             t = ln.strip()
             if t == "@@PFHEAD@@":
-                d = self.pf_decl(0)
+                d = self.pf_decl(0) if ahead else ""
                 if d:
                     out.append("    " + d + " " + self.pf_code(0).rstrip())
                 continue
             if t.startswith("@@PFDECL"):
                 i = int(t[len("@@PFDECL"):-2])
-                d = self.pf_decl(i + 1)
+                d = self.pf_decl(i + ahead)
                 if d:
                     out.append("    " + d)
                 continue
             if "@@PF" in ln:
                 i = int(ln.split("@@PF", 1)[1].split("@@", 1)[0])
-                ln = ln.replace(f"@@PF{i}@@", self.pf_code(i + 1) if i + 1 < n else "")
+                ln = ln.replace(f"@@PF{i}@@", self.pf_code(i + ahead) if i + ahead < n else "")
             out.append(ln)
         self.em.lines = out
 
@@ -462,16 +496,34 @@ def _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flo
 
 def emit_gg_process(name: str, pdg: List[int]) -> Dict:
     """g g -> t t~ + n g, fused: the colour-flow amplitudes J stay in
-    registers and the colour sum runs in the same kernel."""
+    registers and the colour sum runs in the same kernel.  Eight lanes share
+    an event (each takes every eighth good helicity) and its kinematics."""
     n_ext, gluon_legs, terms, n_diag, flows, C, cden, sched = _gg_setup(pdg)
     ncol = len(flows)
     order = sched.low_pressure_order()
 
-    def helicity_body(dist: int, den_index=None) -> List[str]:
+    # The lanes of one event share its kinematics: a probe pass over the body
+    # lists every momentum sum and propagator denominator a routine call
+    # needs; the kernel forms them once per event into LDS rows, and the
+    # helicity body loads each call's values two calls ahead.
+    probe = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
+    pb = GGBody(sched, pdg, probe, lds_momenta=True, prefetch=True)
+    for a in order:
+        pb.amplitude(a)
+        probe.w(" }")
+    keys = list(dict.fromkeys(k for k in map(GGBody.den_key, pb.calls) if k is not None))
+    den_index = {k: i for i, k in enumerate(keys)}
+    masks = list(dict.fromkeys(m for c in pb.calls if c is not None for m in c[1:] if isinstance(m, int)
+                               if c[0] != "den"))
+    kin_index = {m: i for i, m in enumerate(masks)}
+
+    def helicity_body(split: bool) -> List[str]:
         em = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
-        body = GGBody(sched, pdg, em, lds_momenta=True, prefetch=True)
-        body.pf_dist = dist
+        body = GGBody(sched, pdg, em, lds_momenta=True, prefetch=True, mom_block="EVB")
+        body.pf_dist = 2
         body.den_index = den_index
+        body.kin_index = kin_index
+        body.kin_split = split
         for a in order:
             body.amplitude(a)
             upd = " ".join(f"acc(J[{f}], a, {re}, {im});" for f, re, im in a.coeffs)
@@ -479,64 +531,49 @@ def emit_gg_process(name: str, pdg: List[int]) -> Dict:
         body.finish()
         return ["  " + ln for ln in em.lines]
 
-    # Two software-pipelined forms of the same arithmetic: momenta loaded two
-    # routine calls ahead (their latency hidden behind a whole call) or one
-    # call ahead (fewer live registers).  The first is faster wherever it
-    # keeps the kernel's occupancy; for the FP32 kernels of six or more legs
-    # that keep the colour-flow sums in registers, it would cost the second
-    # wave per SIMD.
+    # Each call's values are loaded from the event's rows two calls ahead.
+    # The matrix-core mode, held to 256 registers for two waves per SIMD,
+    # loads the four components of a sum one by one: with 16-byte loads the
+    # compiler's allocation of that mode spills about 4 KB per lane (g g ->
+    # t t~ g g), with 4-byte loads nothing.  Both forms give the same bits.
     lines = [f"    cx<T> J[{ncol}];", f"    for (int s = 0; s < {ncol}; ++s) J[s] = mk<T>((T)0, (T)0);"]
-    den_prologue = ""
-    j2_regs = "false"
-    if n_ext <= 5:
-        lines += helicity_body(2)
-    else:
-        # The FP64 kernels (one block of two waves per SIMD pair) also take
-        # the propagator denominators from a per-event LDS table filled
-        # before the helicity loop; their selection mode keeps its colour
-        # accumulators in registers to leave the LDS to the table.  Not in
-        # FP32, whose two waves per SIMD could not both hold the table.
-        probe = Emitter(n_ext, [i < 2 for i in range(n_ext)], [abs(x) == 6 for x in pdg])
-        pb = GGBody(sched, pdg, probe, lds_momenta=True, prefetch=True)
-        for a in order:
-            pb.amplitude(a)
-            probe.w(" }")
-        keys = list(dict.fromkeys(k for k in map(GGBody.den_key, pb.calls) if k is not None))
-        den_index = {k: i for i, k in enumerate(keys)}
-        den_prologue = den_table_lines(keys, pb.inmask)
-        j2_regs = "sizeof(T) == 8"
-        lines += (["    if constexpr (kDenTable) {"] + helicity_body(2, den_index)
-                  + ["    } else if constexpr (sizeof(T) == 8 || MODE == 2) {"] + helicity_body(2)
-                  + ["    } else {"] + helicity_body(1) + ["    }"])
+    lines += (["    if constexpr (MODE != 4) {"] + helicity_body(False) + ["    } else {"] + helicity_body(True)
+              + ["    }"])
     colour = (["      TC mc = (TC)0;"] + ["  " + ln for ln in colour_sum_lines(C, cden)]
               + ["      const double me = (double)mc;"])
     flops_hel = sched.flops_per_helicity() + 2 * ncol * ncol + 4 * ncol + 90 * n_ext
     return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "\n".join(lines),
-                    colour="\n".join(colour), den_prologue=den_prologue, j2_regs=j2_regs)
+                    colour="\n".join(colour), kin_prologue=kin_table_lines(masks, keys, pb.inmask),
+                    n_kin=len(masks), n_den=len(keys), hel_lanes=8)
 
 
-def den_table_lines(keys: List[tuple], inmask: int) -> str:
-    """Kernel prologue filling sden[k*BLOCK + lane] with 1/(P^2 - m^2) of
-    every distinct propagator of the event, computed exactly as the
-    helicity loop would (same partial sums, same order)."""
-    B = "MGME_ME_BLOCK"
-    out = ["  // Propagator denominators of the event, the same for every helicity:",
-           "  // computed once here, loaded in the helicity loop (FP64 kernels).",
-           "  constexpr bool kDenTable = sizeof(T) == 8;",
-           f"  __shared__ double sden[kDenTable ? {len(keys)} * {B} : 1];",
-           "  if constexpr (kDenTable) {"]
+def kin_table_lines(masks: List[int], keys: List[tuple], inmask: int) -> str:
+    """Kernel prologue filling the event's kinematics rows: skin row r with
+    the flow-in momentum of the legs in masks[r] (as T), sden row k with
+    1/(P^2 - m^2) of denominator keys[k] (computed in double, then taken to
+    T).  Each value is formed exactly as the helicity loop formed it before
+    (same partial sums, same order), so the rows hold the same bits; every
+    lane of the event computes them, its first lane stores them."""
+    B = "EVB"
+    out = ["  // The event's momentum sums and propagator denominators, the same for",
+           "  // every helicity: formed once here, loaded in the helicity loop.",
+           f"  __shared__ T skin[{max(len(masks), 1)} * 4 * {B}];",
+           f"  __shared__ T sden[{max(len(keys), 1)} * {B}];"]
+    for r, m in enumerate(masks):
+        out.append(f"  {{ double kd[4]; flow_momentum_lds<{m}u, {inmask}u, NEXT, {B}>(kd, smom, lane);")
+        out.append(f"    if (sub == 0) {{ T* p = skin + ({r} * {B} + lane) * 4; "
+                   "p[0] = (T)kd[0]; p[1] = (T)kd[1]; p[2] = (T)kd[2]; p[3] = (T)kd[3]; } }")
     for i, k in enumerate(keys):
         if k[0] == "vvv":
             _, m1, m2, mass = k
-            out.append(f"    {{ double k1d[4]; flow_momentum_lds<{m1}u, {inmask}u, NEXT, {B}>(k1d, smom, lane); "
+            out.append(f"  {{ double k1d[4]; flow_momentum_lds<{m1}u, {inmask}u, NEXT, {B}>(k1d, smom, lane); "
                        f"double k2d[4]; flow_momentum_lds<{m2}u, {inmask}u, NEXT, {B}>(k2d, smom, lane);")
-            out.append("      const double Pd[4] = {k1d[0] + k2d[0], k1d[1] + k2d[1], k1d[2] + k2d[2], k1d[3] + k2d[3]};")
-            out.append(f"      sden[{i} * {B} + lane] = inv_virt(Pd, {mass}); }}")
+            out.append("    const double Pd[4] = {k1d[0] + k2d[0], k1d[1] + k2d[1], k1d[2] + k2d[2], k1d[3] + k2d[3]};")
+            out.append(f"    if (sub == 0) sden[{i} * {B} + lane] = (T)inv_virt(Pd, {mass}); }}")
         else:
             _, m, mass = k
-            out.append(f"    {{ double Pd[4]; flow_momentum_lds<{m}u, {inmask}u, NEXT, {B}>(Pd, smom, lane); "
-                       f"sden[{i} * {B} + lane] = inv_virt(Pd, {mass}); }}")
-    out.append("  }")
+            out.append(f"  {{ double Pd[4]; flow_momentum_lds<{m}u, {inmask}u, NEXT, {B}>(Pd, smom, lane); "
+                       f"if (sub == 0) sden[{i} * {B} + lane] = (T)inv_virt(Pd, {mass}); }}")
     return "\n".join(out)
 
 
@@ -670,7 +707,7 @@ def emit_ee_process(name: str, pdg: List[int]) -> Dict:
     w = lambda s: lines.append("    " + s)
     lam = lambda i: f"((hc >> {3 - i}) & 1 ? 1 : -1)"
     w("double q[4][4];")
-    w("for (int i = 0; i < 4; ++i) load_mom_lds<MGME_ME_BLOCK>(q[i], smom, lane, i);")
+    w("for (int i = 0; i < 4; ++i) load_mom_lds<EVB>(q[i], smom, lane, i);")
     w(f"const wf<T> x0 = ext_bra<T>(q[0], 0.0, {lam(0)}, true);   // vbar(e+)")
     w(f"const wf<T> x1 = ext_ket<T>(q[1], 0.0, {lam(1)}, false);  // u(e-)")
     w(f"const wf<T> x2 = ext_ket<T>(q[2], 0.0, {lam(2)}, true);   // v(mu+)")
@@ -691,7 +728,7 @@ def emit_ee_process(name: str, pdg: List[int]) -> Dict:
     w("}")
     meta = dict(name=name, pdg=pdg, n_ext=4, n_diagrams=2, n_terms=2, ncol=1, cden=1, n_currents=4,
                 n_amps=2, gs_power=0, spin_colour_avg=4, ident=1, kind="ee",
-                flops_per_hel=2 * 128 + 2 * 30 + 20, flops_per_event=40, body="\n".join(lines),
+                flops_per_hel=2 * 128 + 2 * 30 + 20, flops_per_event=40, body="\n".join(lines), hel_lanes=4,
                 colour="      const double me = (double)((TC)J[0].re * (TC)J[0].re + (TC)J[0].im * (TC)J[0].im);")
     return meta
 
@@ -710,6 +747,13 @@ namespace {name} {{
 
 constexpr int NEXT = {n_ext};
 constexpr int NCOL = {ncol};
+// HL lanes evaluate one event, lane `sub` taking its good helicities
+// sub, sub + HL, ...; a block holds EVB events.
+constexpr int HL = {hel_lanes};
+constexpr int EVB = MGME_ME_BLOCK / HL;
+
+// Blocks of a launch over nevt events.
+inline unsigned me_blocks(long long nevt) {{ return (unsigned)((nevt + EVB - 1) / EVB); }}
 
 // T: precision of the diagrams; TC: precision of the colour quadratic form.
 // MODE 0: |M|^2 summed over the good helicities into out[e];
@@ -718,7 +762,7 @@ constexpr int NCOL = {ncol};
 //         Jout[(ih*NCOL + s)*ldo + e] (single precision) for the matrix-core colour sum;
 // MODE 3: as MODE 0, and for the helicity and colour choice each helicity's
 //         |M_h|^2 (before normalisation) into aux[ih*lda + e] and
-//         sum_h |J_s|^2 into aux[(nhel + s)*lda + e] (accumulated in LDS);
+//         sum_h |J_s|^2 into aux[(nhel + s)*lda + e];
 // MODE 4: as MODE 0, with the colour sum of every helicity on the matrix
 //         cores of the wave (single-precision J split into two half-precision
 //         parts, at most 32 flows).
@@ -729,93 +773,116 @@ template <typename T, int MODE, typename TC = double>
 __global__ void __launch_bounds__(MGME_ME_BLOCK) __attribute__((amdgpu_waves_per_eu(MODE == 4 ? 2 : 1)))
 me_kernel(const double* __restrict__ mom, long long nevt, long long ld, const MeArgs args, double* __restrict__ out,
           long long ldo, float2* __restrict__ Jout, double* __restrict__ aux, long long lda) {{
-  const long long e_raw = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  // MODE 4 keeps every lane of a wave to the end (the colour sum runs across
-  // the wave's lanes): lanes past the batch evaluate its last event and store
-  // nothing
-  if constexpr (MODE != 4) {{
-    if (e_raw >= nevt) return;
-  }}
+  const int tid = threadIdx.x;
+  const int lane = tid / HL;  // the event's column in the block's LDS rows
+  const int sub = tid % HL;
+  const long long e_raw = (long long)blockIdx.x * EVB + lane;
+  // every lane stays to the end (block barriers; MODE 4 also needs the whole
+  // wave): lanes past the batch evaluate its last event and store nothing
   const bool e_live = e_raw < nevt;
   const long long e = e_live ? e_raw : nevt - 1;
-  const int lane = threadIdx.x;
   mfma_half8 cfa[MODE == 4 ? 2 : 1];
   if constexpr (MODE == 4) {{
     const mfma_half8* cf = (const mfma_half8*)args.cfrag;
-    cfa[0] = cf[lane & 63];
-    cfa[1] = cf[64 + (lane & 63)];
+    cfa[0] = cf[tid & 63];
+    cfa[1] = cf[64 + (tid & 63)];
   }}
-  // per-lane jamp^2 accumulators (MODE 3): in registers where LDS is needed
-  // for the denominator table, else in LDS, [flow][lane of the block]
-  constexpr bool kJ2Regs = {j2_regs};
-  __shared__ double j2[MODE == 3 && !kJ2Regs ? NCOL * MGME_ME_BLOCK : 1];
+  // per-lane jamp^2 accumulators (MODE 3): in registers in FP64 (whose one
+  // wave per SIMD leaves room), else in LDS, [flow][lane of the block]; the
+  // event's sum over its lanes is formed in LDS at the end
+  constexpr bool kJ2Regs = sizeof(T) == 8;
+  __shared__ double j2[MODE == 3 ? NCOL * MGME_ME_BLOCK : 1];
   double j2r[MODE == 3 && kJ2Regs ? NCOL : 1];
   if constexpr (MODE == 3) {{
 #pragma unroll
     for (int s = 0; s < NCOL; ++s) {{
       if constexpr (kJ2Regs) j2r[s] = 0.0;
-      else j2[s * MGME_ME_BLOCK + lane] = 0.0;
+      else j2[s * MGME_ME_BLOCK + tid] = 0.0;
     }}
   }}
-  // The lane's momenta stay in LDS: every momentum-dependent quantity is
-  // derived again inside the helicity loop where it is needed, instead of
-  // being held in registers across it.
-  __shared__ double smom[NEXT * 4 * MGME_ME_BLOCK];
-#pragma unroll
-  for (int i = 0; i < NEXT; ++i)
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) smom[(i * 4 + mu) * MGME_ME_BLOCK + lane] = mom[(long long)(i * 4 + mu) * ld + e];
+  // The event's momenta in LDS, loaded by its lanes together; every
+  // momentum-dependent quantity of the helicity loop is read from LDS where
+  // it is needed instead of being held in registers across it.
+  __shared__ double smom[NEXT * 4 * EVB];
+  for (int k = sub; k < NEXT * 4; k += HL) smom[k * EVB + lane] = mom[(long long)k * ld + e];
+  __syncthreads();
   const double mt = args.mt;
-{den_prologue}
-  // The good helicities are summed in groups of MGME_HEL_GROUP, the group
-  // sums in group order.  A lane takes groups blockIdx.y, blockIdx.y +
-  // gridDim.y, ...: all of them when gridDim.y == 1; otherwise each group sum
-  // goes to aux[g*lda + e] and the helicity-sum kernel adds them in the same
-  // order, so every launch shape gives the same bits.
-  double total = 0.0;
-  const int ngroup = (args.nhel + MGME_HEL_GROUP - 1) / MGME_HEL_GROUP;
-  for (int g = blockIdx.y; g < ngroup; g += gridDim.y) {{
+{kin_prologue}
+  __syncthreads();
   double part = 0.0;
-  const int hend = args.nhel < (g + 1) * MGME_HEL_GROUP ? args.nhel : (g + 1) * MGME_HEL_GROUP;
-  for (int ih = g * MGME_HEL_GROUP; ih < hend; ++ih) {{
+  const int nit = (args.nhel + HL - 1) / HL;
+#pragma unroll 1
+  for (int it = 0; it < nit; ++it) {{
+    // a lane without a helicity left evaluates the last one (the wave's
+    // matrix-core step in MODE 4 needs every lane) and drops the value
+    int ih = it * HL + sub;
+    const bool h_live = ih < args.nhel;
+    if (!h_live) ih = args.nhel - 1;
     const int hc = args.hel[ih];
 {body}
+    // Values are pinned before a store that only some lanes make, and the
+    // sums take them through selects: otherwise the compiler sinks the whole
+    // evaluation into the lanes' branch, where it needs far more registers.
     if constexpr (MODE == 2) {{
 #pragma unroll
-      for (int s = 0; s < NCOL; ++s)
-        Jout[((long long)ih * NCOL + s) * ldo + e] = make_float2((float)J[s].re, (float)J[s].im);
+      for (int s = 0; s < NCOL; ++s) {{
+        pin(J[s].re);
+        pin(J[s].im);
+      }}
+      if (e_live && h_live) {{
+#pragma unroll
+        for (int s = 0; s < NCOL; ++s)
+          Jout[((long long)ih * NCOL + s) * ldo + e] = make_float2((float)J[s].re, (float)J[s].im);
+      }}
     }} else if constexpr (MODE == 4) {{
-      part += colour_mfma_lane<NCOL>(J, cfa);
+      const double m = colour_mfma_lane<NCOL>(J, cfa);
+      part += h_live ? m : 0.0;
     }} else {{
 {colour}
       if constexpr (MODE == 1) {{
-        out[(long long)ih * ldo + e] = me * args.factor;
+        double v = me * args.factor;
+        pin(v);
+        if (e_live && h_live) out[(long long)ih * ldo + e] = v;
       }} else {{
-        part += me;
+        part += h_live ? me : 0.0;
         if constexpr (MODE == 3) {{
-          aux[(long long)ih * lda + e] = me;
+          double v = me;
+          pin(v);
+          if (e_live && h_live) aux[(long long)ih * lda + e] = v;
 #pragma unroll
           for (int s = 0; s < NCOL; ++s) {{
             const double a2 = (double)J[s].re * (double)J[s].re + (double)J[s].im * (double)J[s].im;
-            if constexpr (kJ2Regs) j2r[s] += a2;
-            else j2[s * MGME_ME_BLOCK + threadIdx.x] += a2;
+            if constexpr (kJ2Regs) j2r[s] += h_live ? a2 : 0.0;
+            else j2[s * MGME_ME_BLOCK + tid] += h_live ? a2 : 0.0;
           }}
         }}
       }}
     }}
   }}
+  // The event's sums: its lanes' partial sums added in lane order, so every
+  // launch shape and batch gives the same bits.
   if constexpr (MODE == 0 || MODE == 3 || MODE == 4) {{
-    if (gridDim.y == 1) total += part;
-    else if (e_live) aux[(long long)g * lda + e] = part;
-  }}
-  }}
-  if constexpr (MODE == 0 || MODE == 3 || MODE == 4) {{
-    if (gridDim.y == 1 && e_live) out[e] = total * args.factor;
-  }}
-  if constexpr (MODE == 3) {{
+    __shared__ double sred[MGME_ME_BLOCK];
+    sred[tid] = part;
+    if constexpr (MODE == 3 && kJ2Regs) {{
 #pragma unroll
-    for (int s = 0; s < NCOL; ++s)
-      aux[(long long)(args.nhel + s) * lda + e] = kJ2Regs ? j2r[s] : j2[s * MGME_ME_BLOCK + threadIdx.x];
+      for (int s = 0; s < NCOL; ++s) j2[s * MGME_ME_BLOCK + tid] = j2r[s];
+    }}
+    __syncthreads();
+    if (sub == 0 && e_live) {{
+      double total = 0.0;
+#pragma unroll
+      for (int i = 0; i < HL; ++i) total += sred[lane * HL + i];
+      out[e] = total * args.factor;
+    }}
+    if constexpr (MODE == 3) {{
+      for (int s = sub; s < NCOL; s += HL) {{
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < HL; ++i) t += j2[s * MGME_ME_BLOCK + lane * HL + i];
+        if (e_live) aux[(long long)(args.nhel + s) * lda + e] = t;
+      }}
+    }}
   }}
 }}
 
@@ -853,8 +920,7 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
   if (sel && prec != 2) return mgme_select_{name}(prec, mom, nevt, ld, args, out, sel, wsp, stream);
   if (prec == 2 && !sel && !per_hel && NCOL <= 32) {{
     // the colour sum on the matrix cores inside the diagram kernel
-    const dim3 grid((unsigned)((nevt + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
-    return mgme_run_{name}_m(grid, mom, nevt, ld, args, out, wsp, stream);
+    return mgme_run_{name}_m(dim3(me_blocks(nevt)), mom, nevt, ld, args, out, wsp, stream);
   }}
   if (prec == 2) {{
     // single-precision diagrams write J, the matrix cores form the colour sum
@@ -868,15 +934,10 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
     float2* J = (float2*)ws;
     double* meh = (double*)(ws + (size_t)nh * NCOL * sizeof(float2) * sub);
     double* jamp2 = meh + (size_t)nh * sub;
-    const int ngroup = (nh + MGME_HEL_GROUP - 1) / MGME_HEL_GROUP;
     for (long long start = 0; start < nevt && err == hipSuccess; start += sub) {{
       const long long n = (nevt - start < sub) ? nevt - start : sub;
-      const unsigned gx = (unsigned)((n + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK);
-      // each helicity's J is written on its own: a small batch spreads the
-      // helicity groups over grid rows
-      const int split = mgme::helicity_split((long long)gx * (MGME_ME_BLOCK / 64), ngroup);
-      me_kernel<float, 2><<<dim3(gx, (unsigned)split), block, 0, stream>>>(mom + start, n, ld, *args, nullptr, sub, J,
-                                                                            nullptr, 0);
+      me_kernel<float, 2><<<dim3(me_blocks(n)), block, 0, stream>>>(mom + start, n, ld, *args, nullptr, sub, J,
+                                                                     nullptr, 0);
       err = hipGetLastError();
       if (err == hipSuccess)
         err = mgme::launch_colour_mfma(n, nh, NCOL, J, sub, args->cfrag, per_hel ? out + start : meh,
@@ -890,7 +951,7 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
     const hipError_t ferr = mgme::ws_release(wsp, ws, stream);
     return err != hipSuccess ? err : ferr;
   }}
-  const dim3 grid((unsigned)((nevt + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
+  const dim3 grid(me_blocks(nevt));
   if (prec == 0) return mgme_run_{name}_d(per_hel, grid, mom, nevt, ld, args, out, ldo, wsp, stream);
   if (prec == 3) return mgme_run_{name}_dc(per_hel, grid, mom, nevt, ld, args, out, ldo, wsp, stream);
   return mgme_run_{name}_f(per_hel, grid, mom, nevt, ld, args, out, ldo, wsp, stream);
@@ -904,33 +965,13 @@ extern "C" hipError_t mgme_run_{name}_{tag}(int per_hel, dim3 grid, const double
                                              const mgme::MeArgs* args, double* out, long long ldo,
                                              const mgme::Workspace* wsp, hipStream_t stream) {{
   using namespace mgme::{name};
+  (void)wsp;
   const dim3 block(MGME_ME_BLOCK);
-  // a batch too small to fill the GPU spreads its helicity groups over grid.y
-  const int ngroup = (args->nhel + MGME_HEL_GROUP - 1) / MGME_HEL_GROUP;
-  if (per_hel) {{
-    // each helicity's value is written on its own
-    const int hsplit = mgme::helicity_split((long long)grid.x * (MGME_ME_BLOCK / 64), ngroup);
-    me_kernel<{T}, 1, {TC}><<<dim3(grid.x, (unsigned)hsplit), block, 0, stream>>>(mom, nevt, ld, *args, out, ldo,
-                                                                                   nullptr, nullptr, 0);
-    return hipGetLastError();
-  }}
-  const size_t part_bytes = sizeof(double) * (size_t)ngroup * (size_t)nevt;
-  int split = mgme::helicity_split((long long)grid.x * (MGME_ME_BLOCK / 64), ngroup);
-  // a caller's workspace too small for the group sums: one row (same bits)
-  if (wsp && wsp->ptr && part_bytes > (size_t)wsp->bytes) split = 1;
-  if (split <= 1) {{
+  if (per_hel)  // each helicity's value is written on its own
+    me_kernel<{T}, 1, {TC}><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
+  else
     me_kernel<{T}, 0, {TC}><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, ldo, nullptr, nullptr, 0);
-    return hipGetLastError();
-  }}
-  double* part = nullptr;
-  hipError_t err = mgme::ws_acquire(wsp, part_bytes, (void**)&part, stream);
-  if (err != hipSuccess) return err;
-  me_kernel<{T}, 0, {TC}><<<dim3(grid.x, (unsigned)split), block, 0, stream>>>(mom, nevt, ld, *args, out, ldo,
-                                                                               nullptr, part, nevt);
-  err = hipGetLastError();
-  if (err == hipSuccess) err = mgme::launch_helicity_sum(nevt, ngroup, part, nevt, args->factor, out, stream);
-  const hipError_t ferr = mgme::ws_release(wsp, part, stream);
-  return err != hipSuccess ? err : ferr;
+  return hipGetLastError();
 }}
 """
 
@@ -942,25 +983,9 @@ extern "C" hipError_t mgme_run_{name}_m(dim3 grid, const double* mom, long long 
                                          const mgme::MeArgs* args, double* out, const mgme::Workspace* wsp,
                                          hipStream_t stream) {{
   using namespace mgme::{name};
-  const dim3 block(MGME_ME_BLOCK);
-  // a batch too small to fill the GPU spreads its helicity groups over grid.y
-  const int ngroup = (args->nhel + MGME_HEL_GROUP - 1) / MGME_HEL_GROUP;
-  const size_t part_bytes = sizeof(double) * (size_t)ngroup * (size_t)nevt;
-  int split = mgme::helicity_split((long long)grid.x * (MGME_ME_BLOCK / 64), ngroup);
-  if (wsp && wsp->ptr && part_bytes > (size_t)wsp->bytes) split = 1;
-  if (split <= 1) {{
-    me_kernel<float, 4><<<grid, block, 0, stream>>>(mom, nevt, ld, *args, out, 0, nullptr, nullptr, 0);
-    return hipGetLastError();
-  }}
-  double* part = nullptr;
-  hipError_t err = mgme::ws_acquire(wsp, part_bytes, (void**)&part, stream);
-  if (err != hipSuccess) return err;
-  me_kernel<float, 4><<<dim3(grid.x, (unsigned)split), block, 0, stream>>>(mom, nevt, ld, *args, out, 0, nullptr,
-                                                                           part, nevt);
-  err = hipGetLastError();
-  if (err == hipSuccess) err = mgme::launch_helicity_sum(nevt, ngroup, part, nevt, args->factor, out, stream);
-  const hipError_t ferr = mgme::ws_release(wsp, part, stream);
-  return err != hipSuccess ? err : ferr;
+  (void)wsp;
+  me_kernel<float, 4><<<grid, dim3(MGME_ME_BLOCK), 0, stream>>>(mom, nevt, ld, *args, out, 0, nullptr, nullptr, 0);
+  return hipGetLastError();
 }}
 """
 
@@ -983,7 +1008,7 @@ extern "C" hipError_t mgme_select_{name}(int prec, const double* mom, long long 
   if (err != hipSuccess) return err;
   for (long long start = 0; start < nevt && err == hipSuccess; start += sub) {{
     const long long n = (nevt - start < sub) ? nevt - start : sub;
-    const dim3 grid((unsigned)((n + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK));
+    const dim3 grid(me_blocks(n));
     if (prec == 0)
       me_kernel<double, 3><<<grid, block, 0, stream>>>(mom + start, n, ld, *args, out + start, 0, nullptr, ws, sub);
     else if (prec == 3)
@@ -1005,8 +1030,7 @@ def kernel_sources(meta: Dict) -> Dict[str, str]:
     """File name -> source for a process evaluated by one fused kernel."""
     title = " ".join(str(x) for x in meta["pdg"])
     name = meta["name"]
-    out = {f"me_{name}_kernel.h": KERNEL_HEADER_TEMPLATE.format(
-        title=title, **{"den_prologue": "", "j2_regs": "false", **meta}),
+    out = {f"me_{name}_kernel.h": KERNEL_HEADER_TEMPLATE.format(title=title, **{"kin_prologue": "", **meta}),
            f"me_{name}.hip": LAUNCH_TEMPLATE.format(title=title, name=name),
            f"me_{name}_sel.hip": SELECT_TEMPLATE.format(title=title, name=name)}
     for tag, T, TC, what in (("d", "double", "double", "FP64 diagrams and colour sum"),

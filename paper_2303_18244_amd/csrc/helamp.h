@@ -474,6 +474,30 @@ template <int BLOCK> __device__ __forceinline__ double load_den_lds(const double
 template <typename T> __device__ __forceinline__ void pf_barrier() {
   if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
 }
+// Kinematics of one event shared by the lanes that evaluate its helicities:
+// row k of the block's table holds a momentum sum as T[4] at
+// s[(k*EVB + col)*4 + mu] (one contiguous 16- or 32-byte load), or a
+// propagator denominator at s[k*EVB + col]; col is the event's column in the
+// block, laundered like the lane index above.
+template <typename T, int EVB>
+__device__ __forceinline__ void load_kin_lds(T out[4], const T* s, int k, int col) {
+  const T* p = s + (k * EVB + fresh_lane(col)) * 4;
+  out[0] = p[0]; out[1] = p[1]; out[2] = p[2]; out[3] = p[3];
+}
+// The same with one load per component: four 4-byte loads instead of one
+// 16-byte load into an aligned register quad, which leaves the register
+// allocator more freedom where a kernel is held to 256 registers.
+template <typename T, int EVB>
+__device__ __forceinline__ void load_kin_lds1(T out[4], const T* s, int k, int col) {
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) out[mu] = s[(k * EVB + fresh_lane(col)) * 4 + mu];
+}
+template <typename T, int EVB> __device__ __forceinline__ T load_tden_lds(const T* s, int k, int col) {
+  return s[k * EVB + fresh_lane(col)];
+}
+// Forces x to be computed here, in every lane, before code that only some
+// lanes run (a store), instead of inside that code.
+template <typename V> __device__ __forceinline__ void pin(V& x) { asm volatile("" : "+v"(x)); }
 template <unsigned MASK, unsigned INMASK, int NEXT>
 __device__ __forceinline__ void sum_legs(double out[4], const double (&r)[NEXT][4]) {
 #pragma unroll

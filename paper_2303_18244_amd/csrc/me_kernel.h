@@ -8,13 +8,12 @@
 
 #define MGME_MAX_HEL 128
 
-// Good helicities per group of the helicity sum (see the generated kernels).
-#define MGME_HEL_GROUP 8
-
 namespace mgme {
 
-// Passed by value as a kernel argument, so that the helicity list is read
-// through the scalar unit: every lane of a wave evaluates the same helicity.
+// Passed by value as a kernel argument.  The helicity list is read from the
+// kernel-argument segment: through the scalar unit where every lane of a wave
+// evaluates the same helicity (the staged kernels), per lane where the lanes
+// of one event take different ones (the fused kernels).
 struct MeArgs {
   double mt;        // top-quark mass (GeV)
   double factor;    // gs^(2k) / (spin-colour average * identical-particle factor * colour denominator)
@@ -81,10 +80,5 @@ inline hipError_t ws_release(const Workspace* ws, void* p, hipStream_t stream) {
 using LaunchFn = hipError_t (*)(int prec, int per_hel, const double* mom, long long nevt, long long ld,
                                 const MeArgs* args, double* out, long long ldo, const SelectArgs* sel,
                                 const Workspace* ws, hipStream_t stream);
-
-// Number of grid rows over which a fused kernel spreads its ngroup helicity
-// groups when `waves` waves of 64 events would leave the GPU underfilled
-// (fewer than four waves per SIMD); 1 for large batches.
-int helicity_split(long long waves, int ngroup);
 
 }  // namespace mgme

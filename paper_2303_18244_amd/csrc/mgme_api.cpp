@@ -163,17 +163,6 @@ int check_batch(const mgme_process* proc, const void* a, const void* b, long lon
 
 namespace mgme {
 
-int helicity_split(long long waves, int ngroup) {
-  int dev = 0, cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
-    cu = 256;
-  const long long target = 16LL * cu;  // four waves on each of the four SIMDs of every CU
-  if (ngroup <= 1 || waves <= 0 || waves >= target) return 1;
-  const long long s = (target + waves - 1) / waves;
-  return (int)(s < ngroup ? s : ngroup);
-}
-
 // Staging bytes per event of a launch (0: none), as the generated launchers
 // lay them out without the helicity and colour choice.  The fused processes
 // (at most 32 flows) form the mixed-precision colour sum inside the diagram
@@ -208,11 +197,6 @@ long long workspace_bytes(const ProcEntry& e, int nhel, long long nevt, int prec
     if (sub > round64) sub = round64;
     return per_event * sub;
   }
-  // a small batch spreads its helicity groups over the grid: one partial sum
-  // per group and event
-  const int ngroup = (nhel + MGME_HEL_GROUP - 1) / MGME_HEL_GROUP;
-  const long long waves = (nevt + MGME_ME_BLOCK - 1) / MGME_ME_BLOCK * (MGME_ME_BLOCK / 64);
-  if (helicity_split(waves, ngroup) > 1) return 8LL * ngroup * nevt;
   return 0;
 }
 

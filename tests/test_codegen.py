@@ -74,11 +74,12 @@ def test_schedule_covers_every_term_once(name):
 
 @pytest.mark.parametrize("name", ["gg_tt", "gg_ttg", "gg_ttgg"])
 def test_software_pipelined_body_is_well_formed(name):
-    """The fused kernels' helicity bodies with momenta (and, for g g -> t t~
-    g g in FP64, denominators) loaded one or two routine calls ahead: no
-    placeholder is left, every prefetched value is declared once, assigned
-    in an earlier statement than the call that uses it, and used once; the
-    per-event denominator table has one row per distinct denominator."""
+    """The fused kernels' helicity bodies with momentum sums and denominators
+    loaded from the event's rows two routine calls ahead: no placeholder is left, every
+    prefetched value is declared once, assigned in an earlier statement than
+    the call that uses it, and used once; the kinematics prologue fills one
+    row per distinct momentum sum and per distinct denominator, and the loop
+    reads every row."""
     import re
 
     from paper_2303_18244_amd.build import PROCESSES
@@ -103,6 +104,8 @@ def test_software_pipelined_body_is_well_formed(name):
                 assigned.setdefault(v, i)
             for v in re.findall(r"load_legs_lds<\d+u, NEXT, \w+>\((pf\d+_r),", ln):
                 assigned.setdefault(v, i)
+            for v in re.findall(r"load_kin_lds1?<T, EVB>\((pf\d+_(?:k1|k2|k3|P)),", ln):
+                assigned.setdefault(v, i)
             for v in re.findall(r"(?:vvv_vec|vvvv_vec|ket_prop|bra_prop|ffv_vec|vvv_amp)<[^>]*>\(([^;]*)\);", ln):
                 for u in re.findall(r"\b(pf\d+_(?:k1|k2|k3|P|den))\b", v):
                     used.setdefault(u, []).append(i)
@@ -115,7 +118,14 @@ def test_software_pipelined_body_is_well_formed(name):
             if v.endswith(("_r", "_dr")):
                 continue
             assert v in used, (name, v)
+    # the event's kinematics rows: one per distinct momentum sum and per
+    # distinct denominator, each filled once, each read by the loop
+    pro = meta["kin_prologue"]
+    krows = [int(r) for r in re.findall(r"T\* p = skin \+ \((\d+) \* EVB \+ lane\) \* 4;", pro)]
+    drows = [int(r) for r in re.findall(r"sden\[(\d+) \* EVB \+ lane\] = \(T\)inv_virt", pro)]
+    assert krows == list(range(meta["n_kin"])) and drows == list(range(meta["n_den"]))
+    assert {int(r) for r in re.findall(r"load_kin_lds1?<T, EVB>\(pf\d+_\w+, skin, (\d+), lane\)", body)} == set(krows)
+    assert {int(r) for r in re.findall(r"load_tden_lds<T, EVB>\(sden, (\d+), lane\)", body)} == set(drows)
     if name == "gg_ttgg":
-        rows = re.findall(r"sden\[(\d+) \* MGME_ME_BLOCK \+ lane\] = inv_virt", meta["den_prologue"])
-        assert [int(r) for r in rows] == list(range(44))
-        assert body.count("if constexpr (kDenTable)") == 1
+        assert meta["n_den"] == 44
+    assert body.count("if constexpr (MODE != 4)") == 1

@@ -209,7 +209,7 @@ def test_select_across_sub_batches(M, oracle_mod):
     against the oracle (offsets of the random numbers and outputs)."""
     torch = _torch()
     name, sqrt_s = "gg_ttggg", 1500.0
-    n = 16384 + 100
+    n = 65536 + 100  # four and a bit staging sub-batches of at most 16384 events
     P = M.Process(M.PROCESSES[name])
     O = oracle_mod.Process(oracle_mod.PROCESSES[name])
     host, _ = oracle_mod.rambo(_masses(P.pdg), sqrt_s, SEED, 0, n)
@@ -217,5 +217,5 @@ def test_select_across_sub_batches(M, oracle_mod):
     r_hel, r_col = rng.random(n), rng.random(n)
     me, hel, col = P.select(_dev(host.transpose(1, 2, 0)), _dev(r_hel), _dev(r_col))
     hel, col = hel.cpu().numpy(), col.cpu().numpy()
-    idx = np.array([0, 1, 16383, 16384, 16385, n - 1] + list(np.random.default_rng(3).choice(n, 10, replace=False)))
+    idx = np.array([0, 1, 65535, 65536, 65537, n - 1] + list(np.random.default_rng(3).choice(n, 10, replace=False)))
     assert _compare_choices(hel[idx], col[idx], host[idx], r_hel[idx], r_col[idx], O, 1e-9) >= len(idx) - 1

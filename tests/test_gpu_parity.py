@@ -296,8 +296,9 @@ def test_determinism_and_ragged_edges(lib_procs):
 def test_staging_edges(lib_procs, name, prec):
     """Ragged batch sizes and a padded leading dimension give the same
     per-event values as one small batch; for the staged process a batch of
-    16684 events spans two 16384-event sub-batches of the staging buffers,
-    and the events on both sides of the boundary equal a small batch's."""
+    65836 events spans five sub-batches of the staging buffers (at most 16384
+    events each), and the events on both sides of the last boundary equal a
+    small batch's."""
     torch = _torch()
     P = _proc(lib_procs, name)
     n = 200
@@ -307,11 +308,11 @@ def test_staging_edges(lib_procs, name, prec):
         b = P.matrix_element(mom[:, :, :m].contiguous(), precision=prec).cpu().numpy()
         np.testing.assert_array_equal(b, a[:m])
     if name == "gg_ttggg":
-        big, _ = P.rambo(1500.0, SEED, 0, 16384 + 300)
+        big, _ = P.rambo(1500.0, SEED, 0, 65536 + 300)
         whole = P.matrix_element(big, precision=prec).cpu().numpy()
         np.testing.assert_array_equal(whole[:n], a)
-        edge = P.matrix_element(big[:, :, 16300:].contiguous(), precision=prec).cpu().numpy()
-        np.testing.assert_array_equal(whole[16300:], edge)
+        edge = P.matrix_element(big[:, :, 65400:].contiguous(), precision=prec).cpu().numpy()
+        np.testing.assert_array_equal(whole[65400:], edge)
         assert np.all(np.isfinite(whole)) and np.all(whole > 0)
     padded = torch.zeros((P.n_ext, 4, 256), dtype=torch.float64, device="cuda")
     padded[:, :, :n] = mom
