@@ -149,6 +149,12 @@ class GGBody:
         # calls ahead straight into its own registers (no sums in the loop)
         self.kin_index: Optional[Dict[int, int]] = None
         self.kin_split = False  # one load per component (load_kin_lds1)
+        # kin_lazy (kernels without prefetching): every momentum sum and
+        # denominator is loaded from the event's rows where it is used, rows
+        # assigned in order of first use
+        self.kin_lazy = False
+        self.kin_rows: Dict[int, int] = {}
+        self.den_rows: Dict[tuple, int] = {}
         self.calls: List[Optional[tuple]] = []  # per routine call: its momentum needs
         if prefetch:
             em.w("@@PFHEAD@@")
@@ -342,6 +348,37 @@ class GGBody:
             out.append(ln)
         self.em.lines = out
 
+    def kin_vec(self, var: str, mask: int) -> str:
+        """Declaration and load of the momentum sum of `mask` as T[4] from
+        the event's rows (lazy form)."""
+        r = self.kin_rows.setdefault(mask, len(self.kin_rows))
+        return f"T {var}[4]; load_kin_lds<T, {self.mom_block}>({var}, skin, {r}, lane);"
+
+    def kin_den(self, key: tuple) -> str:
+        """Load of a propagator denominator from the event's rows (lazy form)."""
+        r = self.den_rows.setdefault(key, len(self.den_rows))
+        return f"load_tden_lds<T, {self.mom_block}>(sden, {r}, lane)"
+
+    def emit_current_kin(self, cur, ins, v, pre) -> None:
+        """A current whose momentum sums and denominator come from the rows."""
+        em, fr = self.em, self.fr
+        r = cur.routine
+        if r == "vvv_vec":
+            c1, c2 = cur.tree.children
+            em.w(f"{{ {pre}{self.kin_vec('k1', c1.mask)} {self.kin_vec('k2', c2.mask)}")
+            em.w(f"  {v} = vvv_vec<T>({fr(ins[0])}, k1, {fr(ins[1])}, k2, "
+                 f"{self.kin_den(('vvv', c1.mask, c2.mask, '0.0'))}); }}")
+        elif r == "vvvv_vec":
+            em.w(f"{{ {pre}{v} = vvvv_vec<T, {cur.tree.s}>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])}, "
+                 f"{self.kin_den(('sum', cur.mask, '0.0'))}); }}")
+        elif r in ("ket_prop", "bra_prop"):
+            em.w(f"{{ {pre}{self.kin_vec('P', cur.mask)}")
+            em.w(f"  {v} = {r}<T>({fr(ins[0])}, {fr(ins[1])}, P, (T)mt, {self.kin_den(('sum', cur.mask, 'mt'))}); }}")
+        elif r == "ffv_vec":
+            em.w(f"{{ {pre}{v} = ffv_vec<T>({fr(ins[0])}, {fr(ins[1])}, {self.kin_den(('sum', cur.mask, '0.0'))}); }}")
+        else:
+            raise ValueError(r)
+
     def fr(self, v: str) -> str:
         fn = self.fresh_fn.get(v, "fresh")
         if self.inplace:
@@ -397,6 +434,10 @@ class GGBody:
         pre = self.prep(ins)
         if self.prefetch:
             self.emit_current_pf(cur, ins, v, pre)
+            self.names[key] = v
+            return v
+        if self.kin_lazy:
+            self.emit_current_kin(cur, ins, v, pre)
             self.names[key] = v
             return v
         if cur.routine == "vvv_vec":
@@ -462,7 +503,8 @@ class GGBody:
             em.w(f"{{ {pre}const cx<T> a = ffv_amp<T>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])});")
         elif a.routine == "vvv_amp":
             m1, m2, m3 = (self.leg_mask(k) for k in a.inputs)
-            em.w(f"{{ {pre}{self.mom('k1', m1)} {self.mom('k2', m2)} {self.mom('k3', m3)}")
+            vec = self.kin_vec if self.kin_lazy else self.mom
+            em.w(f"{{ {pre}{vec('k1', m1)} {vec('k2', m2)} {vec('k3', m3)}")
             em.w(f"  const cx<T> a = vvv_amp<T>({fr(ins[0])}, k1, {fr(ins[1])}, k2, {fr(ins[2])}, k3);")
         else:
             em.w(f"{{ {pre}const cx<T> a = vvvv_amp<T, {a.s}>({fr(ins[0])}, {fr(ins[1])}, {fr(ins[2])}, "
@@ -578,7 +620,7 @@ def kin_table_lines(masks: List[int], keys: List[tuple], inmask: int) -> str:
 
 
 def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefetch: int = 6,
-                   inplace: bool = False, lds: bool = False) -> Dict:
+                   inplace: bool = False, lds: bool = False, kin: bool = True) -> Dict:
     """g g -> t t~ + n g, staged for processes whose colour-flow vector does
     not fit in registers.  The amplitude vertices, in low-register-pressure
     order, are split into `n_chunks` kernels.  Each kernel keeps at most
@@ -591,7 +633,10 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
         kernel keeps computing;
       - a flow already folded in the same kernel goes to an overflow slot
         (a kernel never reads back its own stores).
-    A colour kernel adds the overflow slots and forms Re(J^dagger C J)."""
+    A colour kernel adds the overflow slots and forms Re(J^dagger C J).
+    kin: the four waves of a block (one helicity each, the same 64 events)
+    share the events' momenta, momentum sums and denominators in LDS rows,
+    which each chunk fills for what it uses."""
     n_ext, gluon_legs, terms, n_diag, flows, C, cden, sched = _gg_setup(pdg)
     ncol = len(flows)
     order = sched.low_pressure_order()
@@ -604,6 +649,7 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
     written: set = set()
     overflow_flow: List[int] = []
     chunk_bodies = []
+    chunk_rows: List[tuple] = []  # per chunk: (mask -> row, denominator key -> row)
     flops_hel = 0
     n_rmw = 0
     for chunk in chunks:
@@ -615,8 +661,9 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
         # compiled for the CPU is exact with and without the barriers: the
         # defect lies in the device compilation of that variant, and a CPU test
         # keeps the generator from emitting it.
-        body = GGBody(sched, pdg, em, fresh_externals=False, inplace=inplace, lds_momenta=lds, mom_block="64",
-                      ext_lds=lds)
+        body = GGBody(sched, pdg, em, fresh_externals=False, inplace=inplace, lds_momenta=lds or kin,
+                      mom_block="64", ext_lds=lds)
+        body.kin_lazy = kin
         uses: Dict[int, List[int]] = {}
         for j, a in enumerate(chunk):
             for f, _, _ in a.coeffs:
@@ -680,6 +727,7 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
         for at, line in sorted(inserts, key=lambda t: -t[0]):
             em.lines.insert(at, line)
         chunk_bodies.append("\n".join(em.lines))
+        chunk_rows.append((dict(body.kin_rows), dict(body.den_rows)))
         flops_hel += sum(FLOPS[a.routine] + FLOPS["acc"] * len(a.coeffs) for a in chunk)
         flops_hel += sum(sched.currents[k].cost for k in body.names if k[0] != "X")
     assert written == set(range(ncol)), "every flow receives a contribution"
@@ -690,8 +738,44 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
     overflow_of = [[s for s, f in enumerate(overflow_flow) if f == fl] for fl in range(ncol)]
     return _gg_meta(name, pdg, n_ext, gluon_legs, terms, n_diag, ncol, cden, sched, flops_hel, "",
                     staged=True, chunk_bodies=chunk_bodies, n_overflow=len(overflow_flow), n_rmw=n_rmw,
+                    kin=kin, chunk_prologues=[staged_kin_lines(k, d, sum(1 << i for i in range(2)))
+                                              for k, d in chunk_rows] if kin else None,
                     flops_exec_per_hel=flops_exec, lds=lds,
                     overflow_of=overflow_of, colour_num=[int(v * cden) for row in C for v in row])
+
+
+def staged_kin_lines(kin_rows: Dict[int, int], den_rows: Dict[tuple, int], inmask: int, nwaves: int = 4) -> str:
+    """Chunk prologue filling the block's kinematics rows for its 64 events:
+    skin row r with the flow-in momentum of its legs (as T), sden row k with
+    1/(P^2 - m^2) (double, then T), each formed exactly as the chunk formed
+    it per lane before.  Wave w (uniform) fills the rows r with r % nwaves
+    == w, each lane its event's column."""
+    rows = [[] for _ in range(nwaves)]
+    B = "64"
+    for m, r in kin_rows.items():
+        rows[r % nwaves].append(
+            f"    {{ double kd[4]; flow_momentum_lds<{m}u, {inmask}u, NEXT, {B}>(kd, smom, lane); "
+            f"T* p = skin + ({r} * {B} + lane) * 4; p[0] = (T)kd[0]; p[1] = (T)kd[1]; p[2] = (T)kd[2]; "
+            "p[3] = (T)kd[3]; }")
+    for k, r in den_rows.items():
+        if k[0] == "vvv":
+            _, m1, m2, mass = k
+            rows[r % nwaves].append(
+                f"    {{ double k1d[4]; flow_momentum_lds<{m1}u, {inmask}u, NEXT, {B}>(k1d, smom, lane); "
+                f"double k2d[4]; flow_momentum_lds<{m2}u, {inmask}u, NEXT, {B}>(k2d, smom, lane); "
+                "const double Pd[4] = {k1d[0] + k2d[0], k1d[1] + k2d[1], k1d[2] + k2d[2], k1d[3] + k2d[3]}; "
+                f"sden[{r} * {B} + lane] = (T)inv_virt(Pd, {mass}); }}")
+        else:
+            _, m, mass = k
+            rows[r % nwaves].append(
+                f"    {{ double Pd[4]; flow_momentum_lds<{m}u, {inmask}u, NEXT, {B}>(Pd, smom, lane); "
+                f"sden[{r} * {B} + lane] = (T)inv_virt(Pd, {mass}); }}")
+    out = [f"  constexpr int NKIN = {max(len(kin_rows), 1)};", f"  constexpr int NDEN = {max(len(den_rows), 1)};"]
+    for w in range(nwaves):
+        out.append(f"  if (wave == {w}) {{")
+        out += rows[w]
+        out.append("  }")
+    return "\n".join(out)
 
 
 def _fact(n: int) -> int:
@@ -1248,6 +1332,26 @@ CHUNK_PROLOGUE_LDS = r"""  const int lane = threadIdx.x & 63;  // event within t
   const double mt = args.mt;"""
 
 
+# The four waves of a block evaluate the same 64 events (one helicity each):
+# the events' momenta are staged once in LDS, and each chunk forms the
+# momentum sums and denominators it uses once per event into LDS rows
+# (NKIN, NDEN and the filling code come from the chunk; see staged_kin_lines).
+CHUNK_PROLOGUE_KIN = r"""  const int lane = threadIdx.x & 63;  // event within the block
+  const int wave = threadIdx.x >> 6;  // helicity slot within the block (uniform)
+  const long long ec = e < nevt ? e : nevt - 1;
+@@ROWS_DECL@@
+  __shared__ double smom[NEXT * 4 * 64];
+  __shared__ T skin[NKIN * 4 * 64];
+  __shared__ T sden[NDEN * 64];
+  for (int k = wave; k < NEXT * 4; k += 4) smom[k * 64 + lane] = mom[(long long)k * ld + ec];
+  __syncthreads();
+  const double mt = args.mt;
+@@ROWS_FILL@@
+  __syncthreads();
+  if (hs >= args.nhel || e >= nevt) return;
+  const int hc = args.hel[hs];"""
+
+
 def _upper_doubled(num: List[int], n: int) -> List[int]:
     """Row-major n x n: 0 below the diagonal, the diagonal, twice the
     off-diagonal entries above it (the matrix is symmetric)."""
@@ -1261,6 +1365,9 @@ def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 1
     nchunk = len(meta["chunk_bodies"])
     prologue = CHUNK_PROLOGUE_LDS if meta.get("lds") else CHUNK_PROLOGUE_REGS
     for c, body in enumerate(meta["chunk_bodies"]):
+        if meta.get("kin"):
+            decl, fill = meta["chunk_prologues"][c].split("\n", 2)[:2], meta["chunk_prologues"][c].split("\n", 2)[2]
+            prologue = CHUNK_PROLOGUE_KIN.replace("@@ROWS_DECL@@", "\n".join(decl)).replace("@@ROWS_FILL@@", fill)
         for tag, T in (("d", "double"), ("f", "float")):
             out[f"me_{meta['name']}_chunk{c}_{tag}.hip"] = CHUNK_TEMPLATE.format(
                 title=title, chunk=c, n_chunks=nchunk, name=meta["name"], n_ext=meta["n_ext"],

@@ -19,6 +19,11 @@ So the generated program is exact with and without the barriers; the wrong
 values came from the device compilation of the barrier variant, not from
 the code generator.  The generator no longer emits that variant, and the
 first test fails if it ever does again.
+
+The host build includes each chunk's prologue that fills the kinematics
+rows (momentum sums and denominators the chunk reads from LDS), run for the
+one event of column 0, so the rows' assignment and contents are checked
+against the oracle too.
 """
 import concurrent.futures as cf
 import os
@@ -87,6 +92,17 @@ void {variant}_chunk{c}(const double (&q)[7][4], int hc, double mt, cx<double>* 
   using T = double;
   constexpr int NEXT = 7;
   (void)Ov;
+  // the kernel's LDS rows, for the one event of column 0
+  const int lane = 0;
+  static double smom[NEXT * 4 * 64];
+  for (int i = 0; i < NEXT; ++i)
+    for (int mu = 0; mu < 4; ++mu) smom[(i * 4 + mu) * 64] = q[i][mu];
+{rows_decl}
+  static T skin[NKIN * 4 * 64];
+  static T sden[NDEN * 64];
+  for (int wave = 0; wave < 4; ++wave) {{
+{rows_fill}
+  }}
 {body}
 }}
 }}  // namespace mgme
@@ -176,7 +192,8 @@ def test_cpu_build_of_both_variants_matches_oracle(meta, oracle_mod, tmp_path):
     units = []
     for variant in ("plain", "barrier"):
         for c, body in enumerate(meta["chunk_bodies"]):
-            text = CHUNK_UNIT.format(c=c, variant=variant, csrc=CSRC,
+            decl, fill = meta["chunk_prologues"][c].split("\n", 2)[:2], meta["chunk_prologues"][c].split("\n", 2)[2]
+            text = CHUNK_UNIT.format(c=c, variant=variant, csrc=CSRC, rows_decl="\n".join(decl), rows_fill=fill,
                                      body=body if variant == "plain" else barrier_variant(body))
             src = tmp_path / f"{variant}_chunk{c}.cpp"
             src.write_text(text)
