@@ -100,10 +100,23 @@ int mgme_process_destroy(mgme_process* proc);
 
 int mgme_process_info(const mgme_process* proc, mgme_info* out);
 
-/* The good-helicity list: codes[i] has bit (n_ext-1-leg) set when that leg
- * has helicity +1.  `codes` holds at least n_hel entries; *n receives the
- * number of good helicities. */
+/* The helicities the process sums: the good ones found at creation unless
+ * mgme_set_helicities restricted them.  codes[i] has bit (n_ext-1-leg) set
+ * when that leg has helicity +1.  `codes` holds at least n_hel entries; *n
+ * receives the number of helicities. */
 int mgme_good_helicities(const mgme_process* proc, int* codes, int* n);
+
+/* Restricts the helicity sum of mgme_matrix_element, mgme_select and the
+ * serving loop to the configurations codes[0..n-1] (helicity codes as
+ * above, strictly increasing, each below n_hel): |M|^2 then sums those
+ * helicities only, as for a polarised or helicity-resolved cross section
+ * (the paper sums over all helicities, section 2; this is the same sum over
+ * a subset, with the same normalisation).  n = 0 restores the good
+ * helicities of mgme_process_create (codes may then be NULL).  The process
+ * must not be in use by a running call or queued request.  Errors: EINVAL
+ * (NULL process, n < 0 or above n_hel, NULL codes with n > 0, a code out of
+ * range or not above the previous one). */
+int mgme_set_helicities(mgme_process* proc, const int* codes, int n);
 
 /* The colour matrix of the trace basis as integer numerators num[n_colour^2]
  * over the common denominator *den, and the basis: basis[s*k + j] is the
@@ -126,11 +139,10 @@ int mgme_rambo(const mgme_process* proc, double sqrt_s, unsigned long long seed,
  * amplitudes in a workspace taken from the stream-ordered allocator
  * (hipMallocAsync) and returned at the end of the call (at most a few GB, on
  * `hip_stream`); the other processes form every precision's colour sum,
- * MGME_MIXED's on the matrix cores, inside the diagram kernel.  A batch too small to give every
- * SIMD several waves spreads its helicities, in groups of 8, over more lanes
- * and takes 8 bytes per group and event for the partial sums; the group sums
- * are added in the same order whatever the batch size, so an event's |M|^2
- * does not depend on the batch it is in.
+ * MGME_MIXED's on the matrix cores, inside the diagram kernel and take no
+ * workspace.  Eight lanes share an event there, each summing every eighth
+ * helicity, and their partial sums are added in lane order: an event's
+ * |M|^2 does not depend on the batch it is in.
  * Errors: EINVAL, EDEVICE (also when the workspace cannot be allocated). */
 int mgme_matrix_element(const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
                         int precision, double* d_me, void* hip_stream);

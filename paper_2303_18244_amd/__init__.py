@@ -30,6 +30,7 @@ DEFAULT_PARAMS = dict(alpha_s=0.118, alpha_em=1.0 / 132.5, sin2w=0.2222, mz=91.1
 
 # Entry points declared in include/mgme.h.
 EXPORTS = ["mgme_process_create", "mgme_process_destroy", "mgme_process_info", "mgme_good_helicities",
+           "mgme_set_helicities",
            "mgme_colour_matrix", "mgme_rambo", "mgme_matrix_element", "mgme_matrix_element_noalloc",
            "mgme_matrix_element_per_helicity",
            "mgme_workspace_bytes", "mgme_select", "mgme_event_weights", "mgme_unweight",
@@ -96,6 +97,7 @@ def lib() -> ctypes.CDLL:
         L.mgme_process_destroy.argtypes = [vp]
         L.mgme_process_info.argtypes = [vp, ctypes.POINTER(Info)]
         L.mgme_good_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.mgme_set_helicities.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_int]
         L.mgme_colour_matrix.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                                          ctypes.POINTER(ctypes.c_int)]
         L.mgme_rambo.argtypes = [vp, ctypes.c_double, u64, u64, i64, i64, dp, dp, vp]
@@ -172,6 +174,16 @@ class Process:
         n = ctypes.c_int()
         _check(lib().mgme_good_helicities(self._h, codes, ctypes.byref(n)))
         return list(codes[: n.value])
+
+    def set_helicities(self, codes=None):
+        """Sums only the helicity codes given (strictly increasing); None or
+        an empty list restores the good helicities."""
+        codes = list(codes or [])
+        arr = (ctypes.c_int * max(len(codes), 1))(*codes)
+        _check(lib().mgme_set_helicities(self._h, arr if codes else None, len(codes)))
+        info = Info()
+        _check(lib().mgme_process_info(self._h, ctypes.byref(info)))
+        self.info = info.as_dict()
 
     def colour_matrix(self):
         """(numerators [n][n], denominator, basis [n][k])."""

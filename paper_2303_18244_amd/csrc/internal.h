@@ -15,8 +15,7 @@ int matrix_element_ws(const mgme_process* proc, const double* d_mom, long long n
 
 // Smallest caller workspace with which a launch of `precision` runs: one
 // sub-batch of 64 events of the staging buffers (0 when the launch needs no
-// staging; the group sums of a small fused batch are then left out, with the
-// same result bits).
+// staging, as the fused processes' launches never do).
 long long workspace_min_bytes(const mgme_process* proc, int precision);
 
 // Device the process was created on.

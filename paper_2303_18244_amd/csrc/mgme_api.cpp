@@ -22,7 +22,9 @@
 struct mgme_process {
   const mgme::ProcEntry* entry;
   int device;
-  mgme::MeArgs args;      // args.hel holds the good helicities
+  mgme::MeArgs args;      // args.hel holds the helicities summed
+  int good[MGME_MAX_HEL]; // the good helicities found at creation
+  int n_good;
   int n_out;
   double mass_out[6];
   double norm_factor;
@@ -314,6 +316,8 @@ int mgme_process_create(int n_in, int n_out, const int* pdg, const mgme_params* 
     delete p;
     return rc;
   }
+  p->n_good = p->args.nhel;
+  for (int i = 0; i < p->n_good; ++i) p->good[i] = p->args.hel[i];
   *out = p;
   return MGME_OK;
 }
@@ -356,6 +360,25 @@ int mgme_good_helicities(const mgme_process* proc, int* codes, int* n) {
   if (!proc || !codes || !n) return fail(MGME_EINVAL, "NULL argument");
   for (int i = 0; i < proc->args.nhel; ++i) codes[i] = proc->args.hel[i];
   *n = proc->args.nhel;
+  return MGME_OK;
+}
+
+int mgme_set_helicities(mgme_process* proc, const int* codes, int n) {
+  if (!proc) return fail(MGME_EINVAL, "process is NULL");
+  if (n == 0) {
+    proc->args.nhel = proc->n_good;
+    for (int i = 0; i < proc->n_good; ++i) proc->args.hel[i] = proc->good[i];
+    return MGME_OK;
+  }
+  const int nall = 1 << proc->entry->n_ext;
+  if (n < 0 || n > nall || n > MGME_MAX_HEL) return fail(MGME_EINVAL, "helicity count out of range");
+  if (!codes) return fail(MGME_EINVAL, "codes is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (codes[i] < 0 || codes[i] >= nall) return fail(MGME_EINVAL, "helicity code out of range");
+    if (i > 0 && codes[i] <= codes[i - 1]) return fail(MGME_EINVAL, "helicity codes not increasing");
+  }
+  proc->args.nhel = n;
+  for (int i = 0; i < n; ++i) proc->args.hel[i] = codes[i];
   return MGME_OK;
 }
 

@@ -142,7 +142,7 @@ def test_oversize_request_is_split_on_the_device(procs):
     mom, _ = P.rambo(1500.0, 5, 0, n)
     ref = P.matrix_element(mom, precision=M.FP64)
     torch.cuda.synchronize()
-    # momenta, result and group sums take 264 bytes per event: 1 MB holds parts of 2560 events
+    # momenta and result take 200 bytes per event: 1 MB holds parts of 4992 events
     S = M.Server(n_slots=2, hbm_budget_bytes=1_000_000)
     out = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
     S.wait(S.submit(P, mom, precision=M.FP64, out=out))

@@ -12,8 +12,7 @@ SEED = 230318244
 
 # process -> (first batch, second smaller batch); the staged process spans
 # several 512-event FP64 (1024-event FP32 and mixed) sub-batches with a
-# ragged tail; the fused processes' small batches take their helicity-group
-# sums from the fixed array.
+# ragged tail; the fused processes take no workspace at all.
 CASES = {
     "gg_tt": (5000, 333),
     "gg_ttgg": (23000, 10500),
