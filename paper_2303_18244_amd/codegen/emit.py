@@ -688,7 +688,7 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
         # defect lies in the device compilation of that variant, and a CPU test
         # keeps the generator from emitting it.
         body = GGBody(sched, pdg, em, fresh_externals=False, inplace=inplace, lds_momenta=lds or kin,
-                      mom_block="64", ext_lds=lds)
+                      mom_block="EV" if kin else "64", ext_lds=lds)
         body.kin_lazy = kin
         uses: Dict[int, List[int]] = {}
         for j, a in enumerate(chunk):
@@ -770,14 +770,15 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
                     overflow_of=overflow_of, colour_num=[int(v * cden) for row in C for v in row])
 
 
-def staged_kin_lines(kin_rows: Dict[int, int], den_rows: Dict[tuple, int], inmask: int, nwaves: int = 4) -> str:
-    """Chunk prologue filling the block's kinematics rows for its 64 events:
+def staged_kin_lines(kin_rows: Dict[int, int], den_rows: Dict[tuple, int], inmask: int, ngroups: int = 8) -> str:
+    """Chunk prologue filling the block's kinematics rows for its EV events:
     skin row r with the flow-in momentum of its legs (as T), sden row k with
     1/(P^2 - m^2) (double, then T), each formed exactly as the chunk formed
-    it per lane before.  Wave w (uniform) fills the rows r with r % nwaves
-    == w, each lane its event's column."""
+    it per lane before.  Rows fall into ngroups groups by r % ngroups; group
+    w is filled by helicity slot w % HB, each lane its event's column."""
+    nwaves = ngroups
     rows = [[] for _ in range(nwaves)]
-    B = "64"
+    B = "EV"
     for m, r in kin_rows.items():
         rows[r % nwaves].append(
             f"    {{ double kd[4]; flow_momentum_lds<{m}u, {inmask}u, NEXT, {B}>(kd, smom, lane); "
@@ -798,7 +799,7 @@ def staged_kin_lines(kin_rows: Dict[int, int], den_rows: Dict[tuple, int], inmas
                 f"sden[{r} * {B} + lane] = (T)inv_virt(Pd, {mass}); }}")
     out = [f"  constexpr int NKIN = {max(len(kin_rows), 1)};", f"  constexpr int NDEN = {max(len(den_rows), 1)};"]
     for w in range(nwaves):
-        out.append(f"  if (wave == {w}) {{")
+        out.append(f"  if (slot == {w} % HB) {{")
         out += rows[w]
         out.append("  }")
     return "\n".join(out)
@@ -1165,17 +1166,23 @@ constexpr int NEXT = {n_ext};
 constexpr long long NCOL = {ncol};
 constexpr long long NOV = {n_overflow};
 
-// The FP32 kernels are held to two waves per SIMD (256 registers): some
-// values spill, but the second wave hides the latency of the folds and
-// spills that a lone wave waits for (measured on g g -> t t~ g g g, mixed:
-// 91.6 -> 76.0 ms per 65536 events).
+// A block of 256 lanes evaluates EV consecutive events (one lane column
+// each) for 256 / EV helicities.
+template <typename T> constexpr int kEV = sizeof(T) == 8 ? {fp64_ev} : 64;
+
+// Held to two waves per SIMD (256 registers) where the block's LDS allows
+// two blocks per CU: some values spill, but the second wave hides the
+// latency of the folds and spills that a lone wave waits for (measured on
+// g g -> t t~ g g g, mixed: 91.6 -> 76.0 ms per 65536 events).
 template <typename T>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kEV<T> < 64 || sizeof(T) == 4 ? 2 : 1)))
 chunk_kernel(const double* __restrict__ mom, long long nevt, long long ld, const MeArgs args,
              cx<T>* __restrict__ Jbuf, cx<T>* __restrict__ Ovbuf, long long ldp) {{
-  // 64 consecutive events per wave, one helicity per wave (uniform)
-  const int hs = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (threadIdx.x >> 6));
-  const long long e = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
+  constexpr int EV = kEV<T>;
+  constexpr int HB = 256 / EV;
+  int hs = blockIdx.y * HB + (int)threadIdx.x / EV;
+  if constexpr (EV == 64) hs = __builtin_amdgcn_readfirstlane(hs);  // one helicity per wave
+  const long long e = (long long)blockIdx.x * EV + (threadIdx.x % EV);
 {prologue}
   cx<T>* __restrict__ Jc = Jbuf + (long long)hs * NCOL * ldp + e;
   cx<T>* __restrict__ Ov = Ovbuf + (long long)hs * NOV * ldp + e;
@@ -1188,9 +1195,11 @@ chunk_kernel(const double* __restrict__ mom, long long nevt, long long ld, const
 }}  // namespace mgme
 
 // {T} diagrams (each precision in a unit of its own, compiled in parallel)
-extern "C" hipError_t mgme_{name}_chunk{chunk}_{tag}(dim3 grid, const double* mom, long long nevt, long long ld,
+extern "C" hipError_t mgme_{name}_chunk{chunk}_{tag}(const double* mom, long long nevt, long long ld,
                                                     const mgme::MeArgs* args, void* Jbuf, void* Ovbuf, long long ldp,
                                                     hipStream_t stream) {{
+  constexpr int EV = mgme::{name}::c{chunk}::kEV<{T}>;
+  const dim3 grid((unsigned)((nevt + EV - 1) / EV), (unsigned)((args->nhel + 256 / EV - 1) / (256 / EV)));
   mgme::{name}::c{chunk}::chunk_kernel<{T}><<<grid, 256, 0, stream>>>(mom, nevt, ld, *args,
       (mgme::cx<{T}>*)Jbuf, (mgme::cx<{T}>*)Ovbuf, ldp);
   return hipGetLastError();
@@ -1362,18 +1371,18 @@ CHUNK_PROLOGUE_LDS = r"""  const int lane = threadIdx.x & 63;  // event within t
   const double mt = args.mt;"""
 
 
-# The four waves of a block evaluate the same 64 events (one helicity each):
-# the events' momenta are staged once in LDS, and each chunk forms the
-# momentum sums and denominators it uses once per event into LDS rows
-# (NKIN, NDEN and the filling code come from the chunk; see staged_kin_lines).
-CHUNK_PROLOGUE_KIN = r"""  const int lane = threadIdx.x & 63;  // event within the block
-  const int wave = threadIdx.x >> 6;  // helicity slot within the block (uniform)
+# The helicity slots of a block evaluate the same EV events: the events'
+# momenta are staged once in LDS, and each chunk forms the momentum sums and
+# denominators it uses once per event into LDS rows (NKIN, NDEN and the
+# filling code come from the chunk; see staged_kin_lines).
+CHUNK_PROLOGUE_KIN = r"""  const int lane = threadIdx.x % EV;  // event within the block
+  const int slot = threadIdx.x / EV;  // helicity slot within the block
   const long long ec = e < nevt ? e : nevt - 1;
 @@ROWS_DECL@@
-  __shared__ double smom[NEXT * 4 * 64];
-  __shared__ T skin[NKIN * 4 * 64];
-  __shared__ T sden[NDEN * 64];
-  for (int k = wave; k < NEXT * 4; k += 4) smom[k * 64 + lane] = mom[(long long)k * ld + ec];
+  __shared__ double smom[NEXT * 4 * EV];
+  __shared__ T skin[NKIN * 4 * EV];
+  __shared__ T sden[NDEN * EV];
+  for (int k = slot; k < NEXT * 4; k += HB) smom[k * EV + lane] = mom[(long long)k * ld + ec];
   __syncthreads();
   const double mt = args.mt;
 @@ROWS_FILL@@
@@ -1388,8 +1397,11 @@ def _upper_doubled(num: List[int], n: int) -> List[int]:
     return [0 if t < s else (num[s * n + t] if t == s else 2 * num[s * n + t]) for s in range(n) for t in range(n)]
 
 
-def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 16384, nb: int = 30) -> Dict[str, str]:
-    """File name -> source for a staged process."""
+def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 16384, nb: int = 30,
+                   fp64_ev: int = 64) -> Dict[str, str]:
+    """File name -> source for a staged process.  fp64_ev: events per block
+    of the FP64 chunk kernels (64 or 32; the FP32 ones take 64)."""
+    assert fp64_ev in (32, 64) and (fp64_ev == 64 or meta.get("kin")), "32-event blocks need the kinematics rows"
     title = " ".join(str(x) for x in meta["pdg"])
     out = {}
     nchunk = len(meta["chunk_bodies"])
@@ -1402,7 +1414,7 @@ def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 1
             out[f"me_{meta['name']}_chunk{c}_{tag}.hip"] = CHUNK_TEMPLATE.format(
                 title=title, chunk=c, n_chunks=nchunk, name=meta["name"], n_ext=meta["n_ext"],
                 ncol=meta["ncol"], n_overflow=max(1, meta["n_overflow"]), body=body, prologue=prologue,
-                tag=tag, T=T)
+                tag=tag, T=T, fp64_ev=fp64_ev)
     sums = []
     for fl, sl in enumerate(meta["overflow_of"]):
         if not sl:
@@ -1412,11 +1424,11 @@ def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 1
         sums.append(f"  {{ cx<T> v = J[{fl}ll * ldp]; v.re += {terms_re}; v.im += {terms_im}; "
                     f"J[{fl}ll * ldp] = v; }}")
     decls = "\n".join(
-        f'extern "C" hipError_t mgme_{meta["name"]}_chunk{c}_{tag}(dim3, const double*, long long, long long, '
+        f'extern "C" hipError_t mgme_{meta["name"]}_chunk{c}_{tag}(const double*, long long, long long, '
         f'const mgme::MeArgs*, void*, void*, long long, hipStream_t);' for c in range(nchunk) for tag in "df")
     calls = "\n".join(
         f"    if (err == hipSuccess) err = (dprec == 0 ? mgme_{meta['name']}_chunk{c}_d : mgme_{meta['name']}_chunk{c}_f)"
-        f"(grid, mom + start, n, ld, args, Jbuf, Ovbuf, sub, stream);" for c in range(nchunk))
+        f"(mom + start, n, ld, args, Jbuf, Ovbuf, sub, stream);" for c in range(nchunk))
     assert meta["ncol"] % nb == 0
     out[f"me_{meta['name']}.hip"] = COLOUR_TEMPLATE.format(
         title=title, name=meta["name"], n_diagrams=meta["n_diagrams"], n_terms=meta["n_terms"],

@@ -93,14 +93,16 @@ void {variant}_chunk{c}(const double (&q)[7][4], int hc, double mt, cx<double>* 
   constexpr int NEXT = 7;
   (void)Ov;
   // the kernel's LDS rows, for the one event of column 0
+  constexpr int EV = 64;
+  constexpr int HB = 4;
   const int lane = 0;
-  static double smom[NEXT * 4 * 64];
+  static double smom[NEXT * 4 * EV];
   for (int i = 0; i < NEXT; ++i)
-    for (int mu = 0; mu < 4; ++mu) smom[(i * 4 + mu) * 64] = q[i][mu];
+    for (int mu = 0; mu < 4; ++mu) smom[(i * 4 + mu) * EV] = q[i][mu];
 {rows_decl}
-  static T skin[NKIN * 4 * 64];
-  static T sden[NDEN * 64];
-  for (int wave = 0; wave < 4; ++wave) {{
+  static T skin[NKIN * 4 * EV];
+  static T sden[NDEN * EV];
+  for (int slot = 0; slot < HB; ++slot) {{
 {rows_fill}
   }}
 {body}
