@@ -663,6 +663,7 @@ def emit_gg_staged(name: str, pdg: List[int], n_chunks: int, budget: int, prefet
     kin: the four waves of a block (one helicity each, the same 64 events)
     share the events' momenta, momentum sums and denominators in LDS rows,
     which each chunk fills for what it uses."""
+    assert not (lds and kin), "external wavefunctions in LDS go with the register-momenta form (kin=False)"
     n_ext, gluon_legs, terms, n_diag, flows, C, cden, sched = _gg_setup(pdg)
     ncol = len(flows)
     order = sched.low_pressure_order()
