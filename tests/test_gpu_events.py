@@ -172,10 +172,11 @@ def test_select_fp64_matches_oracle(M, oracle_mod, name):
 
 
 def test_denominator_table_same_bits(M, oracle_mod):
-    """g g -> t t~ g g in FP64: the plain kernel takes the propagator
-    denominators from its per-event table, the selection kernel recomputes
-    them for every helicity with the same operations; the |M|^2 of both
-    must agree bit for bit."""
+    """g g -> t t~ g g in FP64: the plain kernel and the selection kernel
+    (which also writes every helicity's value and the flow weights) take the
+    momentum sums and denominators from the same per-event rows and add the
+    event's lane sums in the same order; the |M|^2 of both must agree bit for
+    bit."""
     torch = _torch()
     n, sqrt_s = 1000, 1500.0
     P = M.Process(M.PROCESSES["gg_ttgg"])
