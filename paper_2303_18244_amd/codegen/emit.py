@@ -1404,7 +1404,10 @@ def _upper_doubled(num: List[int], n: int) -> List[int]:
 def staged_sources(meta: Dict, workspace_bytes: int = 12 << 30, max_sub: int = 16384, nb: int = 30,
                    fp64_ev: int = 64) -> Dict[str, str]:
     """File name -> source for a staged process.  fp64_ev: events per block
-    of the FP64 chunk kernels (64 or 32; the FP32 ones take 64)."""
+    of the FP64 chunk kernels (64, or 32 to let two blocks share a CU; the
+    FP32 ones take 64).  The 32-event form is generated but has not been
+    built: the compiler's register allocation of one such chunk had not
+    finished after 25 minutes."""
     assert fp64_ev in (32, 64) and (fp64_ev == 64 or meta.get("kin")), "32-event blocks need the kinematics rows"
     title = " ".join(str(x) for x in meta["pdg"])
     out = {}
