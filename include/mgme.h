@@ -142,7 +142,8 @@ int mgme_rambo(const mgme_process* proc, double sqrt_s, unsigned long long seed,
  * MGME_MIXED's on the matrix cores, inside the diagram kernel and take no
  * workspace.  Eight lanes share an event there, each summing every eighth
  * helicity, and their partial sums are added in lane order: an event's
- * |M|^2 does not depend on the batch it is in.
+ * |M|^2 does not depend on the batch it is in.  Batches above 2^28 events
+ * run as consecutive launches of at most 2^28 events.
  * Errors: EINVAL, EDEVICE (also when the workspace cannot be allocated). */
 int mgme_matrix_element(const mgme_process* proc, const double* d_mom, long long nevt, long long ld,
                         int precision, double* d_me, void* hip_stream);

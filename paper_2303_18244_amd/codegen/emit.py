@@ -1032,6 +1032,19 @@ extern "C" hipError_t mgme_launch_{name}(int prec, int per_hel, const double* mo
                                           hipStream_t stream) {{
   using namespace mgme::{name};
   const dim3 block(MGME_ME_BLOCK);
+  // One launch covers at most 2^28 events (2^31 lanes at eight lanes per
+  // event): larger batches run as consecutive parts, each event's result
+  // the same.  (The workspace paths below already run in sub-batches.)
+  constexpr long long kMaxLaunch = 1ll << 28;
+  const bool ws_path = sel || (prec == 2 && (per_hel || NCOL > 32));
+  if (nevt > kMaxLaunch && !ws_path) {{
+    hipError_t err = hipSuccess;
+    for (long long s0 = 0; s0 < nevt && err == hipSuccess; s0 += kMaxLaunch) {{
+      const long long n = nevt - s0 < kMaxLaunch ? nevt - s0 : kMaxLaunch;
+      err = mgme_launch_{name}(prec, per_hel, mom + s0, n, ld, args, out + s0, ldo, sel, wsp, stream);
+    }}
+    return err;
+  }}
   if (sel && prec != 2) return mgme_select_{name}(prec, mom, nevt, ld, args, out, sel, wsp, stream);
   if (prec == 2 && !sel && !per_hel && NCOL <= 32) {{
     // the colour sum on the matrix cores inside the diagram kernel

@@ -332,3 +332,26 @@ def test_colour_matrix_export_matches_oracle(lib_procs, oracle_procs):
         for i, bi in enumerate(basis):
             for j, bj in enumerate(basis):
                 assert num[i][j] * oden == Co[idx[tuple(bi)], idx[tuple(bj)]] * den
+
+
+def test_huge_batch_runs_in_parts(lib_procs):
+    """A fused batch above 2^28 events (more than 2^31 lanes at eight lanes
+    per event) runs as consecutive launches; events on both sides of the
+    part boundary equal a small batch's, bit for bit.  g g -> t t~ with
+    2^28 + 96 events: 34 GB of momenta."""
+    torch = _torch()
+    free, _ = torch.cuda.mem_get_info()
+    if free < 48 << 30:
+        pytest.skip("needs 48 GB of free device memory")
+    P = _proc(lib_procs, "gg_tt")
+    n = (1 << 28) + 96
+    mom, _ = P.rambo(1500.0, SEED, 0, n)
+    for prec in (0, 1):
+        me = P.matrix_element(mom, precision=prec)
+        lo = (1 << 28) - 64
+        part = P.matrix_element(mom[:, :, lo:].contiguous(), precision=prec)
+        assert torch.equal(me[lo:], part)
+        assert bool(torch.isfinite(me).all()) and bool((me > 0).all())
+        del me, part
+    del mom
+    torch.cuda.empty_cache()
