@@ -206,8 +206,9 @@ def test_select_reduced_precision(M, oracle_mod, name, prec):
 
 
 def test_select_across_sub_batches(M, oracle_mod):
-    """g g -> t t~ g g g: a batch of two staging sub-batches; events from both
-    against the oracle (offsets of the random numbers and outputs)."""
+    """g g -> t t~ g g g: a batch over five staging sub-batches; events on both
+    sides of every boundary against the oracle (offsets of the random numbers
+    and outputs)."""
     torch = _torch()
     name, sqrt_s = "gg_ttggg", 1500.0
     n = 65536 + 100  # four and a bit staging sub-batches of at most 16384 events
@@ -218,5 +219,6 @@ def test_select_across_sub_batches(M, oracle_mod):
     r_hel, r_col = rng.random(n), rng.random(n)
     me, hel, col = P.select(_dev(host.transpose(1, 2, 0)), _dev(r_hel), _dev(r_col))
     hel, col = hel.cpu().numpy(), col.cpu().numpy()
-    idx = np.array([0, 1, 65535, 65536, 65537, n - 1] + list(np.random.default_rng(3).choice(n, 10, replace=False)))
+    edges = [b + d for b in (16384, 32768, 49152, 65536) for d in (-1, 0)]
+    idx = np.array([0, 1] + edges + [65537, n - 1] + list(np.random.default_rng(3).choice(n, 10, replace=False)))
     assert _compare_choices(hel[idx], col[idx], host[idx], r_hel[idx], r_col[idx], O, 1e-9) >= len(idx) - 1
