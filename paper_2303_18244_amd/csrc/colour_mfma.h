@@ -42,10 +42,13 @@ typedef float mfma_floatx16 __attribute__((ext_vector_type(16)));
 // L supplies the flows 0..7 and 16..23 of lane L+32's event (exchanged with a
 // swap of the wave's halves).  Each lane then holds the partial dot product
 // of its K half for both tiles; the two halves of an event are added once
-// more after one swap.
+// more after one swap.  With at most 16 flows the second K step holds only
+// zeros (of J and of C), so it is left out: the same sums, exactly, with half
+// the matrix-core instructions, splits and swaps.
 template <int NCOL, typename CX>
 __device__ __forceinline__ double colour_mfma_lane(const CX* J, const mfma_half8 cfrag[2]) {
   static_assert(NCOL <= 32, "one 32-row tile");
+  constexpr int KS = NCOL > 16 ? 2 : 1;  // K steps of 16 flows
   const int lane = threadIdx.x & 63;
   const bool upper = lane >= 32;
   float mx = 0.0f;
@@ -59,7 +62,7 @@ __device__ __forceinline__ double colour_mfma_lane(const CX* J, const mfma_half8
   // lane (lane xor 32) and comes back as the partner event's half
   mfma_half8 m_rh[2], m_rl[2], m_ih[2], m_il[2], x_rh[2], x_rl[2], x_ih[2], x_il[2];
 #pragma unroll
-  for (int ks = 0; ks < 2; ++ks)
+  for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int f0 = 16 * ks + j, f1 = f0 + 8;
@@ -85,7 +88,7 @@ __device__ __forceinline__ double colour_mfma_lane(const CX* J, const mfma_half8
     v = __builtin_bit_cast(mfma_half8, w);
   };
 #pragma unroll
-  for (int ks = 0; ks < 2; ++ks) {
+  for (int ks = 0; ks < KS; ++ks) {
     swap_halves(x_rh[ks]);
     swap_halves(x_rl[ks]);
     swap_halves(x_ih[ks]);
@@ -100,7 +103,7 @@ __device__ __forceinline__ double colour_mfma_lane(const CX* J, const mfma_half8
     mfma_floatx16 dr = {}, di = {};
     mfma_half8 brh[2], brl[2], bih[2], bil[2];
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
+    for (int ks = 0; ks < KS; ++ks) {
       brh[ks] = mine ? m_rh[ks] : x_rh[ks];
       brl[ks] = mine ? m_rl[ks] : x_rl[ks];
       bih[ks] = mine ? m_ih[ks] : x_ih[ks];
@@ -114,7 +117,7 @@ __device__ __forceinline__ double colour_mfma_lane(const CX* J, const mfma_half8
     // of K step i/8 of this lane
     double acc = 0.0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
+    for (int i = 0; i < 8 * KS; ++i) {
       const int ks = i / 8, j = i % 8;
       const double xre = (double)(float)brh[ks][j] + (double)(float)brl[ks][j];
       const double xim = (double)(float)bih[ks][j] + (double)(float)bil[ks][j];
